@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the 3D r2c/c2r path on one MI355X.
+
+One step = one pair: r2c x -> X, then c2r X -> y (with a work buffer, so X is
+kept; no feedback from y to x).  The input is a 512^3 real field with a
+k^(-5/3) random-phase spectrum (|k| <= 170), unit RMS, seed 3, resident in HBM
+before timing starts.  FP32 is the headline line; the FP64 run is reported in
+the same line under "f64".
+
+Timing: W untimed warm-up pairs, then K pairs on torch's current stream between
+two HIP events, bracketed by device synchronisation.  A second timed region
+runs the same K pairs pass by pass (fft3d_run_pass: the same kernels and launch
+shapes) with an event pair around every kernel, which gives each kernel's
+average duration for the roofline entry.
+
+Roofline: the paper's steps read and write the array once each (plane step:
+s*N real + 2*s*M complex; each column pass: 2*s*M in and out), with s the
+bytes per real scalar, N = n0*n1*n2 and M = n0*n1*(n2/2+1).  achieved = those
+algorithmic bytes of one launch of the dominant kernel / its average duration;
+peak = 8 TB/s (MI355X HBM3E).
+
+CPU baseline: the FP64 oracle (oracle/, all host threads) on one pair of the
+same field (the sample), reported as pairs/s; the GPU result of that pair is
+compared with it (relative L2 over all stored scalars).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "r2c+c2r pairs/s & % HBM peak at 512³ FP32/FP64; p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = {0: "plane_r2c", 1: "n1_fwd", 2: "n0_fwd", 3: "n0_inv", 4: "n1_inv", 5: "plane_c2r"}
+
+
+def pass_bytes(pid: int, shape, elem: int) -> int:
+    n0, n1, n2 = shape
+    N = n0 * n1 * n2
+    M = n0 * n1 * (n2 // 2 + 1)
+    if pid in (0, 5):
+        return elem * N + 2 * elem * M
+    return 4 * elem * M
+
+
+def pair_bytes_alg(shape, elem: int) -> int:
+    n0, n1, n2 = shape
+    N = n0 * n1 * n2
+    M = n0 * n1 * (n2 // 2 + 1)
+    return 2 * (elem * N + 3 * 2 * elem * M)
+
+
+def pair_bytes_min(shape, elem: int) -> int:
+    n0, n1, n2 = shape
+    N = n0 * n1 * n2
+    M = n0 * n1 * (n2 // 2 + 1)
+    return 2 * (elem * N + 2 * elem * M)
+
+
+def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields):
+    plan = F.Plan(*shape, dtype=dtype)
+    desc = plan.describe()
+    elem = 4 if dtype == "f32" else 8
+    x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
+    X = F.empty_complex(plan)
+    y = F.empty_real(plan)
+    work = F.empty_complex(plan)
+    s = torch.cuda.current_stream()
+
+    def pair():
+        F.fft3d_r2c(plan, x, X, s)
+        F.fft3d_c2r(plan, X, y, work, s)
+
+    for _ in range(warmup):
+        pair()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        pair()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+
+    # per-kernel: the same pairs, pass by pass, an event pair around each kernel
+    seq = [(p, x, X) if p == 0 else (p, X, X) for p in desc["r2c_passes"]]
+    cur = X
+    for p in desc["c2r_passes"]:
+        if p == 5:
+            seq.append((p, cur, y))
+        else:
+            seq.append((p, cur, work))
+            cur = work
+    evs = []
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        for p, a, b in seq:
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(s)
+            F.fft3d_run_pass(plan, p, a, b, s)
+            eb.record(s)
+            evs.append((p, ea, eb))
+    torch.cuda.synchronize()
+    tot = {}
+    for p, ea, eb in evs:
+        tot[p] = tot.get(p, 0.0) + ea.elapsed_time(eb)
+    kern = {}
+    for p, t in tot.items():
+        avg_ms = t / steps
+        gbs = pass_bytes(p, shape, elem) / (avg_ms * 1e-3) / 1e9
+        kern[PASS_NAMES[p]] = {"avg_us": round(avg_ms * 1e3, 2), "alg_bytes": pass_bytes(p, shape, elem),
+                               "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(tot, key=lambda p: tot[p])
+    n = shape[0] * shape[1] * shape[2]
+    flops_pair = 2 * 5 * n * math.log2(n)
+    b_alg = pair_bytes_alg(shape, elem)
+    b_min = pair_bytes_min(shape, elem)
+    out = {
+        "pairs_s": 1e3 / ms,
+        "ms_per_pair": ms,
+        "hbm_frac_alg": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "hbm_frac_min": b_min / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "GB_s_alg": b_alg / (ms * 1e-3) / 1e9,
+        "gflops": flops_pair / (ms * 1e-3) / 1e9,
+        "B_alg_per_pair": b_alg,
+        "kernels": kern,
+        "dominant": PASS_NAMES[dom],
+        "roofline": {"bound": "hbm", "achieved": kern[PASS_NAMES[dom]]["GB_s"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kern[PASS_NAMES[dom]]["frac"], "traffic": None,
+                     "kernel": PASS_NAMES[dom], "alg_bytes_per_launch": pass_bytes(dom, shape, elem),
+                     "avg_us": kern[PASS_NAMES[dom]]["avg_us"]},
+        "plan": {"plane": desc["plane"]["kind"], "n0_W": desc["n0_pass"]["W"]},
+    }
+    # one more pair for the accuracy check against the oracle sample
+    pair()
+    torch.cuda.synchronize()
+    res = (plan, x, X, y)
+    return out, res
+
+
+def copy_bandwidth(torch) -> float:
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--dtypes", default="f32,f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this path has no multi-GPU form (the slab exchange "
+              "across devices is a design, not built); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1406_5597_amd import fft3d as F
+    from paper_1406_5597_amd import fields
+
+    n = args.size
+    shape = (n, n, n)
+    t0 = time.time()
+    x64 = fields.k53_field(shape, seed=3)
+    print("# field %s generated in %.1f s" % (shape, time.time() - t0), file=sys.stderr, flush=True)
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    results, keep = {}, {}
+    for d in dtypes:
+        print("# timing %s ..." % d, file=sys.stderr, flush=True)
+        results[d], keep[d] = run_dtype(F, torch, x64, shape, d, args.steps, args.warmup, fields)
+        print("# %s: %.3f ms/pair, %.1f pairs/s, dominant %s %.1f GB/s" % (
+            d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
+            results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth(torch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        head = dtypes[0]
+        plan, x, X, y = keep[head]
+        xin = fields.as_dtype(x64, head).astype(np.float64)
+        print("# oracle sample (one %s pair, FP64) ..." % (shape,), file=sys.stderr, flush=True)
+        t0 = time.time()
+        Xo = oracle.r2c(xin)
+        yo = oracle.c2r(Xo, n)
+        dt = time.time() - t0
+        cpu = {"value": 1.0 / dt, "unit": "pairs/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "one r2c+c2r pair of the same %dx%dx%d field (%s-rounded input, computed in FP64), "
+                         "%.1f s wall" % (n, n, n, head, dt)}
+        for d in dtypes:
+            p, xd, Xd, yd = keep[d]
+            if d != head:
+                continue
+            results[d]["rel_l2_r2c"] = fields.rel_l2(Xd.cpu().numpy(), Xo)
+            results[d]["rel_l2_c2r"] = fields.rel_l2(yd.cpu().numpy(), yo)
+        del Xo, yo
+
+    head = dtypes[0]
+    r = results[head]
+    line = {
+        "metric": METRIC,
+        "value": round(r["pairs_s"], 2),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_pair"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic: %d^3 real field, random-phase k^-5/3 spectrum (|k|<=%d), unit RMS, seed 3" % (
+            n, n // 3),
+        "config": {"workload": "3D r2c+c2r pair %dx%dx%d %s (r2c x->X, c2r X->y with work), natural-order "
+                               "n0 x n1 x %d spectrum" % (n, n, n, head, n // 2 + 1),
+                   "shape": list(shape), "parallelism": "single GPU"},
+        "hbm_frac_alg": round(r["hbm_frac_alg"], 4),
+        "hbm_frac_min": round(r["hbm_frac_min"], 4),
+        "GB_s_alg": round(r["GB_s_alg"], 1),
+        "gflops": round(r["gflops"], 1),
+        "kernels": r["kernels"],
+        "roofline": r["roofline"],
+        "cpu_baseline": cpu,
+        "copy_GB_s": round(copy_gbs, 1),
+    }
+    for k in ("rel_l2_r2c", "rel_l2_c2r"):
+        if k in r:
+            line[k] = r[k]
+    for d in dtypes[1:]:
+        o = results[d]
+        line[d] = {"value": round(o["pairs_s"], 2), "unit": "pairs/s", "ms_per_step": round(o["ms_per_pair"], 4),
+                   "hbm_frac_alg": round(o["hbm_frac_alg"], 4), "hbm_frac_min": round(o["hbm_frac_min"], 4),
+                   "gflops": round(o["gflops"], 1), "kernels": o["kernels"], "roofline": o["roofline"]}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

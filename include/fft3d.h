@@ -1,0 +1,195 @@
+/*
+ * fft3d.h -- C interface of libfft3d, a 3D real-to-complex / complex-to-real
+ * FFT for one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper: Chatterjee, Verma & Chaudhuri, "Transpose-free Fast
+ * Fourier Transform for Turbulence Simulation", Sec. 2, problem statement):
+ * the forward transform (r2c) takes a real n0 x n1 x n2 array x to the complex
+ * n0 x n1 x (n2/2+1) array
+ *
+ *   X[k0,k1,k2] = sum_{j0,j1,j2} x[j0,j1,j2] exp(-2 pi i (k0 j0/n0 + k1 j1/n1 + k2 j2/n2)),
+ *
+ * 0 <= k2 <= n2/2; the inverse (c2r) maps such an array back to a real one.
+ * It is computed the transpose-free way (Sec. 2.1 items 1 and 3, Sec. 2.2):
+ * 2D r2c transforms of the n0 planes, then a length-n0 c2c transform that
+ * reads the strided n0 columns of the natural-order spectrum in place; the
+ * inverse runs the steps in reverse order.
+ *
+ * Conventions (the paper is silent; these are FFTW's, which it builds on):
+ *   - minus sign forward, plus sign inverse, no normalisation:
+ *     c2r(r2c(x)) = n0*n1*n2 * x;
+ *   - C order (n2 fastest); complex values interleaved (re, im) in the real
+ *     type of the plan (float2 / double2);
+ *   - the spectrum is in natural order: X[k0,k1,k2] at offset
+ *     (k0*n1 + k1)*(n2/2+1) + k2, index k >= n/2 standing for k - n;
+ *   - c2r of an arbitrary half spectrum X returns Re(IDFT3(E(X))), where E
+ *     completes the k2 axis with E[k0,k1,n2-k2] = conj(X[-k0,-k1,k2]) and
+ *     keeps the k2 = 0 and k2 = n2/2 planes as given (equivalently: the
+ *     imaginary parts of the k2 = 0 and n2/2 bins of each row are dropped
+ *     after the n0 and n1 inverse passes).
+ *
+ * Memory and threads:
+ *   - every array is device memory owned by the caller; a plan owns only its
+ *     twiddle table (device) and its host description;
+ *   - fft3d_r2c, fft3d_c2r and fft3d_batch_submit allocate nothing and do
+ *     not synchronise: they enqueue kernels on the given stream and return;
+ *   - a plan is immutable after creation and may be used from several
+ *     streams or host threads at once, as long as every concurrent call has
+ *     its own output and work buffers;
+ *   - a plan belongs to the device that was current when it was created;
+ *     calls must be made with that device current.
+ *
+ * Errors are returned as negative codes, never thrown; fft3d_last_error()
+ * gives a thread-local message for the last failing call on this thread.
+ */
+#ifndef FFT3D_H
+#define FFT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft3d_plan_s* fft3d_plan_t;
+
+/* Real type of a plan.  All arithmetic of the plan's kernels is in this type;
+ * twiddle factors are computed in extended precision on the host and rounded
+ * to it once. */
+typedef enum { FFT3D_F32 = 0, FFT3D_F64 = 1 } fft3d_dtype;
+
+enum {
+    FFT3D_OK = 0,
+    FFT3D_ERR_INVALID_ARG = -1, /* null/overlapping pointers, bad sizes or dtype */
+    FFT3D_ERR_UNSUPPORTED = -2, /* extents the GPU path does not cover */
+    FFT3D_ERR_NOMEM = -3,       /* plan table allocation failed */
+    FFT3D_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch error) */
+    FFT3D_ERR_BUDGET = -5,      /* reserved for admission control */
+    FFT3D_ERR_ALIGN = -6        /* a pointer is not aligned to the plan's complex type */
+};
+
+/* Transform directions of a batch item. */
+enum { FFT3D_R2C = 0, FFT3D_C2R = 1, FFT3D_ROUNDTRIP = 2 };
+
+/* Plan flags for fft3d_plan_ex. */
+enum { FFT3D_PLAN_HOST_ONLY = 1 /* build schedules/tables on the host only; cannot execute */ };
+
+/* Library version (major*10000 + minor*100 + patch). */
+int fft3d_version(void);
+
+/* Create a plan for an n0 x n1 x n2 real array in the given dtype.
+ * Supported extents: every n >= 1 whose prime factors are 2 and 3, with
+ * n0, n1 <= 4096, n2 even and n2 <= 8192.  Other extents return
+ * FFT3D_ERR_UNSUPPORTED; n < 1, a bad dtype or out == NULL return
+ * FFT3D_ERR_INVALID_ARG.  Builds the radix schedules and the twiddle table
+ * (host, FP64 via long double) and uploads the table to the current device
+ * (hipMalloc + hipMemcpy: the only allocation the library makes).
+ * On success *out receives the plan. */
+int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out);
+
+/* As fft3d_plan; flags = FFT3D_PLAN_HOST_ONLY builds no device state (usable
+ * for fft3d_plan_describe / fft3d_plan_twiddles, not for transforms). */
+int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out);
+
+/* Free a plan and its device table.  NULL is accepted.  The caller must make
+ * sure no enqueued work still uses the plan. */
+int fft3d_plan_destroy(fft3d_plan_t p);
+
+/* Bytes of the optional c2r work buffer: n0*n1*(n2/2+1) complex values. */
+size_t fft3d_work_bytes(fft3d_plan_t p);
+/* Bytes of the real array (n0*n1*n2 reals) and of the spectrum. */
+size_t fft3d_real_bytes(fft3d_plan_t p);
+size_t fft3d_complex_bytes(fft3d_plan_t p);
+
+/* Forward transform (paper Sec. 2.1 steps 1 and 3, Sec. 2.2).
+ * x: device, n0*n1*n2 reals, C order, not modified.
+ * X: device, n0*n1*(n2/2+1) complex, written in natural order.
+ * x and X must not overlap; both aligned to the complex type (8 or 16 bytes).
+ * Enqueued on `stream` (0 = the null stream). */
+int fft3d_r2c(fft3d_plan_t p, const void* x, void* X, hipStream_t stream);
+
+/* Inverse transform (the same steps in reverse order, Sec. 2.1).
+ * X: device, n0*n1*(n2/2+1) complex.  y: device, n0*n1*n2 reals.
+ * work: device buffer of fft3d_work_bytes(p), or NULL.  With work, X is
+ * preserved; without, X is used as scratch and overwritten.  X, y and work
+ * must not overlap; all aligned to the complex type. */
+int fft3d_c2r(fft3d_plan_t p, void* X, void* y, void* work, hipStream_t stream);
+
+/* One item of a batch.
+ *   R2C:       in = x (real), out = X (complex); mid, work unused.
+ *   C2R:       in = X (complex), out = y (real); work optional as in fft3d_c2r.
+ *   ROUNDTRIP: in = x, mid = X (receives r2c(x)), out = y = c2r(X); work
+ *              optional (with work, mid keeps the spectrum). */
+typedef struct {
+    fft3d_plan_t plan;
+    int dir;
+    const void* in;
+    void* mid;
+    void* out;
+    void* work;
+} fft3d_batch_item;
+
+/* Enqueue every item on `stream`.  All items are validated first; if any is
+ * invalid nothing is enqueued (all or nothing) and the index of the first bad
+ * item is in fft3d_last_error().  Items run in order on the stream. */
+int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream);
+
+/* The passes a transform is made of, for fft3d_run_pass.  The forward
+ * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
+ * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan is
+ * "fused" when a whole n1 x (n2/2+1) plane fits in LDS (the plane pass then
+ * does both in-plane axes) and "split" otherwise; fft3d_plan_describe reports
+ * which, and the pass lists of both directions. */
+enum {
+    FFT3D_PASS_PLANE_R2C = 0, /* in: real x; out: spectrum (after the plane step) */
+    FFT3D_PASS_N1_FWD = 1,    /* in/out: spectrum (in == out allowed) */
+    FFT3D_PASS_N0_FWD = 2,    /* in/out: spectrum (in == out allowed); paper step 3 */
+    FFT3D_PASS_N0_INV = 3,    /* in/out: spectrum (in == out allowed) */
+    FFT3D_PASS_N1_INV = 4,    /* in/out: spectrum (in == out allowed) */
+    FFT3D_PASS_PLANE_C2R = 5  /* in: spectrum; out: real y */
+};
+
+/* Enqueue one pass of the plan on `stream` (no allocation, no sync): the same
+ * kernel and launch shape the transforms use.  Pointers as for fft3d_r2c /
+ * fft3d_c2r; spectrum in/out may be equal, real/spectrum must not overlap.
+ * Returns FFT3D_ERR_INVALID_ARG for a pass the plan does not have. */
+int fft3d_run_pass(fft3d_plan_t p, int pass, const void* in, void* out, hipStream_t stream);
+
+/* Static message for an error code. */
+const char* fft3d_strerror(int code);
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* fft3d_last_error(void);
+
+/* JSON description of the plan (extents, schedules, strategy, tile widths,
+ * launch grids) written to buf (NUL-terminated, truncated to len).  Returns
+ * the full length needed, excluding the NUL, or a negative code. */
+int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len);
+
+/* Copy the plan's twiddle table for one axis to host memory, as FP64 values of
+ * the table exactly as the kernels use it (rounded to the plan's dtype).
+ * which: 0 = n0 stages, 1 = n1 stages, 2 = n2/2 stages, 3 = r2c split roots
+ * exp(-2 pi i k/n2) for k = 0..n2/2.  out: 2*count doubles (re, im).
+ * Returns the number of complex entries of that table, or a negative code;
+ * copies min(count, entries). */
+int64_t fft3d_plan_twiddles(fft3d_plan_t p, int which, double* out, int64_t count);
+
+/* Slab decomposition over p devices (design of the multi-device form of the
+ * paper's exchange, Sec. 2.2, Fig. 3): device q holds rows [q*n0/p, (q+1)*n0/p)
+ * of the n0 x ncols natural-order array after step 1 and owns columns
+ * [r*ncols/p, (r+1)*ncols/p) for step 3.  The block device src sends to device
+ * dst is the strided vector: first element offset (within src's slab), count
+ * rows, blocklen contiguous elements per row, stride between rows -- the
+ * analogue of an MPI vector type.  out[4] = {first, count, blocklen, stride};
+ * the same block lands at offset out[4+0] of dst's natural-order column slab
+ * (n0 rows of ncols/p) with stride out[4+3]: out has 8 entries.
+ * Requires p >= 1, n0 % p == 0, ncols % p == 0, 0 <= src, dst < p. */
+int fft3d_exchange_block(int64_t n0, int64_t ncols, int64_t p, int64_t src, int64_t dst, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT3D_H */

@@ -1,0 +1,407 @@
+// fft3d_abi.cpp -- the extern "C" entry points of libfft3d (see include/fft3d.h).
+//
+// Validation, error codes and thread-local messages; plan creation (the only
+// place the library allocates device memory); and the call sequences of the
+// forward and inverse transforms.  Nothing here synchronises the device
+// except plan creation, which uploads the twiddle table.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fft3d.h"
+#include "fft3d_internal.hpp"
+
+struct fft3d_plan_s {
+    fft3d::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(FFT3D_ERR_HIP, m);
+}
+
+std::once_flag g_init_once;
+hipError_t g_init_status = hipSuccess;
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Checks shared by the transforms: a plan with device state, used on its own
+// device.
+int check_plan(const fft3d_plan_s* h, const char* who)
+{
+    if (!h) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": plan is NULL");
+    if (!h->p.has_device)
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": plan was created host-only");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev != h->p.device) {
+        char b[160];
+        snprintf(b, sizeof b, "%s: plan belongs to device %d but device %d is current", who, h->p.device, dev);
+        return fail(FFT3D_ERR_INVALID_ARG, b);
+    }
+    return FFT3D_OK;
+}
+
+int check_ptr(const void* ptr, int align, const char* who, const char* name)
+{
+    if (!ptr) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": " + name + " is NULL");
+    if ((uintptr_t)ptr % (uintptr_t)align)
+        return fail(FFT3D_ERR_ALIGN, std::string(who) + ": " + name + " is not aligned to the complex type");
+    return FFT3D_OK;
+}
+
+size_t real_bytes(const fft3d::Plan& p) { return (size_t)p.N * (size_t)p.elem; }
+size_t cplx_bytes(const fft3d::Plan& p) { return (size_t)p.M * 2 * (size_t)p.elem; }
+
+int validate_r2c(const fft3d_plan_s* h, const void* x, const void* X)
+{
+    const char* who = "fft3d_r2c";
+    int rc = check_plan(h, who);
+    if (rc) return rc;
+    const int a = 2 * h->p.elem;
+    if ((rc = check_ptr(x, a, who, "x"))) return rc;
+    if ((rc = check_ptr(X, a, who, "X"))) return rc;
+    if (overlaps(x, real_bytes(h->p), X, cplx_bytes(h->p)))
+        return fail(FFT3D_ERR_INVALID_ARG, "fft3d_r2c: x and X overlap (out-of-place only)");
+    return FFT3D_OK;
+}
+
+int validate_c2r(const fft3d_plan_s* h, const void* X, const void* y, const void* work)
+{
+    const char* who = "fft3d_c2r";
+    int rc = check_plan(h, who);
+    if (rc) return rc;
+    const int a = 2 * h->p.elem;
+    if ((rc = check_ptr(X, a, who, "X"))) return rc;
+    if ((rc = check_ptr(y, a, who, "y"))) return rc;
+    const size_t cb = cplx_bytes(h->p), rb = real_bytes(h->p);
+    if (overlaps(X, cb, y, rb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_c2r: X and y overlap");
+    if (work) {
+        if ((rc = check_ptr(work, a, who, "work"))) return rc;
+        if (overlaps(work, cb, X, cb) || overlaps(work, cb, y, rb))
+            return fail(FFT3D_ERR_INVALID_ARG, "fft3d_c2r: work overlaps X or y");
+    }
+    return FFT3D_OK;
+}
+
+// Forward: step 1 (plane r2c), then step 3 (n0 columns, in place on X).
+int enqueue_r2c(const fft3d::Plan& p, const void* x, void* X, hipStream_t s)
+{
+    hipError_t e;
+    if (p.fused_plane) {
+        e = fft3d::launch_plane_r2c(p, x, X, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c plane kernel");
+    } else {
+        e = fft3d::launch_rows_r2c(p, x, X, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
+        if (p.n1 > 1) {
+            e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, X, X, false, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
+        }
+    }
+    if (p.n0 > 1) {
+        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, X, X, false, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n0 columns kernel");
+    }
+    return FFT3D_OK;
+}
+
+// Inverse: step 3 reversed (n0 columns, into work or in place), then step 1
+// reversed (plane c2r).
+int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t s)
+{
+    hipError_t e;
+    void* scratch = work ? work : X;
+    const void* cur = X;
+    if (p.n0 > 1) {
+        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, cur, scratch, true, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n0 columns kernel");
+        cur = scratch;
+    }
+    if (p.fused_plane) {
+        e = fft3d::launch_plane_c2r(p, cur, y, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r plane kernel");
+    } else {
+        if (p.n1 > 1) {
+            e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, cur, scratch, true, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
+            cur = scratch;
+        }
+        e = fft3d::launch_rows_c2r(p, cur, y, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
+    }
+    return FFT3D_OK;
+}
+
+template <typename T> void round_table(const std::vector<long double>& src, std::vector<T>& dst)
+{
+    dst.resize(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = (T)src[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int fft3d_version(void) { return 100; }
+
+int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out)
+{
+    if (!out) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: out is NULL");
+    *out = nullptr;
+    if (flags & ~FFT3D_PLAN_HOST_ONLY) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: unknown flags");
+    fft3d_plan_s* h = new (std::nothrow) fft3d_plan_s;
+    if (!h) return fail(FFT3D_ERR_NOMEM, "fft3d_plan: out of host memory");
+    std::string why;
+    int rc = fft3d::plan_build_host(h->p, n0, n1, n2, dtype, why);
+    if (rc) {
+        delete h;
+        return fail(rc, "fft3d_plan: " + why);
+    }
+    if (!(flags & FFT3D_PLAN_HOST_ONLY)) {
+        std::call_once(g_init_once, [] { g_init_status = fft3d::kernels_init(); });
+        if (g_init_status != hipSuccess) {
+            delete h;
+            return hip_fail(g_init_status, "fft3d_plan: kernel set-up");
+        }
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "fft3d_plan: hipGetDevice");
+        }
+        const fft3d::Plan& p = h->p;
+        size_t bytes = (size_t)std::max<int64_t>(p.tw_count, 1) * 2 * (size_t)p.elem;
+        std::vector<float> tf;
+        std::vector<double> td;
+        const void* host;
+        if (p.dtype == FFT3D_F64) {
+            round_table(p.tw_host, td);
+            td.resize(bytes / sizeof(double), 0.0);
+            host = td.data();
+        } else {
+            round_table(p.tw_host, tf);
+            tf.resize(bytes / sizeof(float), 0.0f);
+            host = tf.data();
+        }
+        void* d = nullptr;
+        e = hipMalloc(&d, bytes);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(FFT3D_ERR_NOMEM, std::string("fft3d_plan: hipMalloc of twiddles: ") + hipGetErrorString(e));
+        }
+        e = hipMemcpy(d, host, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            delete h;
+            return hip_fail(e, "fft3d_plan: twiddle upload");
+        }
+        h->p.d_tw = d;
+        h->p.device = dev;
+        h->p.has_device = true;
+    }
+    *out = h;
+    return FFT3D_OK;
+}
+
+int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out)
+{
+    return fft3d_plan_ex(n0, n1, n2, dtype, 0, out);
+}
+
+int fft3d_plan_destroy(fft3d_plan_t h)
+{
+    if (!h) return FFT3D_OK;
+    int rc = FFT3D_OK;
+    if (h->p.d_tw) {
+        hipError_t e = hipFree(h->p.d_tw);
+        if (e != hipSuccess) rc = hip_fail(e, "fft3d_plan_destroy");
+    }
+    delete h;
+    return rc;
+}
+
+size_t fft3d_work_bytes(fft3d_plan_t h) { return h ? cplx_bytes(h->p) : 0; }
+size_t fft3d_real_bytes(fft3d_plan_t h) { return h ? real_bytes(h->p) : 0; }
+size_t fft3d_complex_bytes(fft3d_plan_t h) { return h ? cplx_bytes(h->p) : 0; }
+
+int fft3d_r2c(fft3d_plan_t h, const void* x, void* X, hipStream_t s)
+{
+    int rc = validate_r2c(h, x, X);
+    if (rc) return rc;
+    return enqueue_r2c(h->p, x, X, s);
+}
+
+int fft3d_c2r(fft3d_plan_t h, void* X, void* y, void* work, hipStream_t s)
+{
+    int rc = validate_c2r(h, X, y, work);
+    if (rc) return rc;
+    return enqueue_c2r(h->p, X, y, work, s);
+}
+
+int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
+{
+    if (n < 0 || (n > 0 && !items)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_submit: bad item array");
+    for (int i = 0; i < n; ++i) {
+        const fft3d_batch_item& it = items[i];
+        int rc;
+        switch (it.dir) {
+        case FFT3D_R2C: rc = validate_r2c(it.plan, it.in, it.out); break;
+        case FFT3D_C2R: rc = validate_c2r(it.plan, it.in, it.out, it.work); break;
+        case FFT3D_ROUNDTRIP:
+            rc = validate_r2c(it.plan, it.in, it.mid);
+            if (!rc) rc = validate_c2r(it.plan, it.mid, it.out, it.work);
+            if (!rc && it.plan && overlaps(it.in, real_bytes(it.plan->p), it.out, real_bytes(it.plan->p)))
+                rc = fail(FFT3D_ERR_INVALID_ARG, "in and out overlap");
+            break;
+        default: rc = fail(FFT3D_ERR_INVALID_ARG, "unknown direction"); break;
+        }
+        if (rc) {
+            char b[64];
+            snprintf(b, sizeof b, "fft3d_batch_submit: item %d: ", i);
+            g_last_error = b + g_last_error;
+            return rc;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        const fft3d_batch_item& it = items[i];
+        int rc = FFT3D_OK;
+        if (it.dir == FFT3D_R2C) rc = enqueue_r2c(it.plan->p, it.in, it.out, s);
+        else if (it.dir == FFT3D_C2R) rc = enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
+        else {
+            rc = enqueue_r2c(it.plan->p, it.in, it.mid, s);
+            if (!rc) rc = enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
+        }
+        if (rc) return rc;
+    }
+    return FFT3D_OK;
+}
+
+int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStream_t s)
+{
+    const char* who = "fft3d_run_pass";
+    int rc = check_plan(h, who);
+    if (rc) return rc;
+    const fft3d::Plan& p = h->p;
+    const int a = 2 * p.elem;
+    if ((rc = check_ptr(in, a, who, "in"))) return rc;
+    if ((rc = check_ptr(out, a, who, "out"))) return rc;
+    const size_t cb = cplx_bytes(p), rb = real_bytes(p);
+    hipError_t e = hipSuccess;
+    switch (pass) {
+    case FFT3D_PASS_PLANE_R2C:
+        if (overlaps(in, rb, out, cb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
+        e = p.fused_plane ? fft3d::launch_plane_r2c(p, in, out, s) : fft3d::launch_rows_r2c(p, in, out, s);
+        break;
+    case FFT3D_PASS_PLANE_C2R:
+        if (overlaps(in, cb, out, rb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
+        e = p.fused_plane ? fft3d::launch_plane_c2r(p, in, out, s) : fft3d::launch_rows_c2r(p, in, out, s);
+        break;
+    case FFT3D_PASS_N1_FWD:
+    case FFT3D_PASS_N1_INV:
+        if (p.fused_plane || p.n1 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n1 pass");
+        if (in != out && overlaps(in, cb, out, cb))
+            return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
+        e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, in, out, pass == FFT3D_PASS_N1_INV, s);
+        break;
+    case FFT3D_PASS_N0_FWD:
+    case FFT3D_PASS_N0_INV:
+        if (p.n0 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n0 pass");
+        if (in != out && overlaps(in, cb, out, cb))
+            return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
+        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV, s);
+        break;
+    default: return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: unknown pass");
+    }
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
+const char* fft3d_strerror(int code)
+{
+    switch (code) {
+    case FFT3D_OK: return "success";
+    case FFT3D_ERR_INVALID_ARG: return "invalid argument";
+    case FFT3D_ERR_UNSUPPORTED: return "unsupported extents";
+    case FFT3D_ERR_NOMEM: return "out of memory";
+    case FFT3D_ERR_HIP: return "HIP runtime error";
+    case FFT3D_ERR_BUDGET: return "over the memory budget";
+    case FFT3D_ERR_ALIGN: return "misaligned pointer";
+    default: return "unknown error code";
+    }
+}
+
+const char* fft3d_last_error(void) { return g_last_error.c_str(); }
+
+int fft3d_plan_describe(fft3d_plan_t h, char* buf, size_t len)
+{
+    if (!h) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan_describe: plan is NULL");
+    std::string d = h->p.describe();
+    if (buf && len) {
+        size_t n = std::min(len - 1, d.size());
+        memcpy(buf, d.data(), n);
+        buf[n] = '\0';
+    }
+    return (int)d.size();
+}
+
+int64_t fft3d_plan_twiddles(fft3d_plan_t h, int which, double* out, int64_t count)
+{
+    if (!h) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan_twiddles: plan is NULL");
+    const fft3d::Plan& p = h->p;
+    int64_t off, cnt;
+    switch (which) {
+    case 0: off = p.off_ax0; cnt = p.tw_count - p.off_ax0; break;
+    case 1: off = p.off_ax1; cnt = p.off_ax0 - p.off_ax1; break;
+    case 2: off = p.off_ax2h; cnt = p.off_post - p.off_ax2h; break;
+    case 3: off = p.off_post; cnt = p.h + 1; break;
+    default: return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan_twiddles: which must be 0..3");
+    }
+    if (count < 0 || (count > 0 && !out)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan_twiddles: bad output");
+    const int64_t m = std::min(count, cnt);
+    for (int64_t i = 0; i < 2 * m; ++i) {
+        long double v = p.tw_host[2 * off + i];
+        out[i] = p.dtype == FFT3D_F64 ? (double)v : (double)(float)v;
+    }
+    return cnt;
+}
+
+int fft3d_exchange_block(int64_t n0, int64_t ncols, int64_t np, int64_t src, int64_t dst, int64_t* out)
+{
+    if (!out || np < 1 || n0 < 1 || ncols < 1 || n0 % np || ncols % np || src < 0 || src >= np || dst < 0 ||
+        dst >= np)
+        return fail(FFT3D_ERR_INVALID_ARG, "fft3d_exchange_block: bad arguments");
+    const int64_t r = n0 / np, c = ncols / np;
+    out[0] = dst * c;  // sender: columns of dst within its r x ncols slab
+    out[1] = r;
+    out[2] = c;
+    out[3] = ncols;
+    out[4] = src * r * c;  // receiver: rows of src within its n0 x c column slab
+    out[5] = r;
+    out[6] = c;
+    out[7] = c;
+    return FFT3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// fft3d_device.hpp -- device building blocks of the 3D r2c/c2r library (gfx950).
+//
+// Complex arithmetic with explicit fused multiply-adds (the library is built
+// with -ffp-contract=off, so the rounding of every expression is fixed by the
+// source and identical in every kernel that inlines it), the radix-2/3/4/8/16
+// DFT butterflies held in registers, and a Stockham autosort stage that runs on
+// lines held in LDS.
+//
+// Stage convention (Stockham, natural-order output).  For a line of length n
+// and a stage of radix R whose preceding stages have product Ns, butterfly
+// j in [0, n/R) reads the R inputs at j + r*(n/R), multiplies input r by the
+// twiddle w_{Ns*R}^{r*(j mod Ns)}, runs the length-R DFT, and writes output r
+// to (j div Ns)*Ns*R + (j mod Ns) + r*Ns.  After the last stage the line holds
+// the DFT in natural order.  w_m = exp(-2 pi i/m) forward, its conjugate for
+// the inverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft3d_sched.hpp"
+
+namespace fft3d {
+
+template <typename T> struct cx_of;
+template <> struct cx_of<float> { using type = float2; };
+template <> struct cx_of<double> { using type = double2; };
+template <typename T> using cx = typename cx_of<T>::type;
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b)
+{
+    cx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// a * w
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> w)
+{
+    return mk<T>(fmaT(a.x, w.x, -(a.y * w.y)), fmaT(a.x, w.y, a.y * w.x));
+}
+// a * conj(w)
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> w)
+{
+    return mk<T>(fmaT(a.x, w.x, a.y * w.y), fmaT(a.y, w.x, -(a.x * w.y)));
+}
+// multiply by w_4 = -i (forward) or +i (inverse)
+template <bool INV, typename T> __device__ __forceinline__ cx<T> rot4(cx<T> a)
+{
+    return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+// multiply by w twiddle from a forward table: w (forward) or conj(w) (inverse)
+template <bool INV, typename T> __device__ __forceinline__ cx<T> twmul(cx<T> a, cx<T> w)
+{
+    return INV ? cmulc<T>(a, w) : cmul<T>(a, w);
+}
+
+// ------------------------------------------------------------ butterflies --
+// In-place length-R DFT of v[0..R): v[k] <- sum_r v[r] w_R^{rk}.
+
+template <bool INV, typename T> __device__ __forceinline__ void dft2(cx<T>* v)
+{
+    cx<T> a = v[0], b = v[1];
+    v[0] = cadd<T>(a, b);
+    v[1] = csub<T>(a, b);
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void dft3(cx<T>* v)
+{
+    const T s = (T)0.86602540378443864676372317075293618; // sin(2 pi/3)
+    cx<T> t = cadd<T>(v[1], v[2]);
+    cx<T> d = csub<T>(v[1], v[2]);
+    cx<T> x0 = v[0];
+    v[0] = cadd<T>(x0, t);
+    cx<T> m = mk<T>(fmaT((T)-0.5, t.x, x0.x), fmaT((T)-0.5, t.y, x0.y));
+    // forward: w_3 = -1/2 - i s, so X1 = m - i s d, X2 = m + i s d
+    cx<T> isd = INV ? mk<T>(-s * d.y, s * d.x) : mk<T>(s * d.y, -s * d.x);
+    v[1] = cadd<T>(m, isd);
+    v[2] = csub<T>(m, isd);
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void dft4(cx<T>* v)
+{
+    cx<T> t0 = cadd<T>(v[0], v[2]);
+    cx<T> t1 = csub<T>(v[0], v[2]);
+    cx<T> t2 = cadd<T>(v[1], v[3]);
+    cx<T> t3 = rot4<INV, T>(csub<T>(v[1], v[3]));
+    v[0] = cadd<T>(t0, t2);
+    v[2] = csub<T>(t0, t2);
+    v[1] = cadd<T>(t1, t3);
+    v[3] = csub<T>(t1, t3);
+}
+
+// z * w_8 (forward w_8 = (c, -c)), inverse conj
+template <bool INV, typename T> __device__ __forceinline__ cx<T> rot8(cx<T> z)
+{
+    const T c = (T)0.70710678118654752440084436210484904;
+    return INV ? mk<T>(c * (z.x - z.y), c * (z.x + z.y)) : mk<T>(c * (z.x + z.y), c * (z.y - z.x));
+}
+// z * w_8^3 (forward (-c, -c)), inverse conj
+template <bool INV, typename T> __device__ __forceinline__ cx<T> rot8_3(cx<T> z)
+{
+    const T c = (T)0.70710678118654752440084436210484904;
+    return INV ? mk<T>(-c * (z.x + z.y), c * (z.x - z.y)) : mk<T>(c * (z.y - z.x), -c * (z.x + z.y));
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void dft8(cx<T>* v)
+{
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<INV, T>(e);
+    dft4<INV, T>(o);
+    o[1] = rot8<INV, T>(o[1]);
+    o[2] = rot4<INV, T>(o[2]);
+    o[3] = rot8_3<INV, T>(o[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = cadd<T>(e[k], o[k]);
+        v[k + 4] = csub<T>(e[k], o[k]);
+    }
+}
+
+// Length 16 as 4 x 4: Y_r = DFT4 of v[r + 4m]; Y_r[k1] *= w_16^{r k1};
+// X[k1 + 4 k2] = DFT4 over r of Y_r[k1].
+template <bool INV, typename T> __device__ __forceinline__ void dft16(cx<T>* v)
+{
+    const T c1 = (T)0.92387953251128675612818318939678829; // cos(pi/8)
+    const T s1 = (T)0.38268343236508977172845998403039887; // sin(pi/8)
+    cx<T> y[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        y[r][0] = v[r];
+        y[r][1] = v[r + 4];
+        y[r][2] = v[r + 8];
+        y[r][3] = v[r + 12];
+        dft4<INV, T>(y[r]);
+    }
+    // twiddles w_16^{r k1}, r, k1 in 1..3 (forward table values; inverse conjugates)
+    const cx<T> w1 = mk<T>(c1, -s1);  // w_16^1
+    const cx<T> w3 = mk<T>(s1, -c1);  // w_16^3
+    const cx<T> w9 = mk<T>(-c1, s1);  // w_16^9
+    y[1][1] = twmul<INV, T>(y[1][1], w1);
+    y[1][2] = rot8<INV, T>(y[1][2]);
+    y[1][3] = twmul<INV, T>(y[1][3], w3);
+    y[2][1] = rot8<INV, T>(y[2][1]);
+    y[2][2] = rot4<INV, T>(y[2][2]);
+    y[2][3] = rot8_3<INV, T>(y[2][3]);
+    y[3][1] = twmul<INV, T>(y[3][1], w3);
+    y[3][2] = rot8_3<INV, T>(y[3][2]);
+    y[3][3] = twmul<INV, T>(y[3][3], w9);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cx<T> z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        dft4<INV, T>(z);
+        v[k1] = z[0];
+        v[k1 + 4] = z[1];
+        v[k1 + 8] = z[2];
+        v[k1 + 12] = z[3];
+    }
+}
+
+template <int R, bool INV, typename T> __device__ __forceinline__ void dftR(cx<T>* v)
+{
+    if constexpr (R == 2) dft2<INV, T>(v);
+    else if constexpr (R == 3) dft3<INV, T>(v);
+    else if constexpr (R == 4) dft4<INV, T>(v);
+    else if constexpr (R == 8) dft8<INV, T>(v);
+    else if constexpr (R == 16) dft16<INV, T>(v);
+}
+
+__device__ __forceinline__ int lds_addr(const LdsLines& L, int w, int i)
+{
+    if (L.lpp >= L.nlines) return w * L.sw + i * L.si;  // one panel (uniform branch)
+    int p = w / L.lpp;
+    int q = w - p * L.lpp;
+    return p * L.sp + q * L.sw + i * L.si;
+}
+
+// One Stockham stage of radix R over all lines in LDS.  EPT: the largest
+// number of elements (lines * n) per thread the caller will ever pass.
+// Ends with a barrier; the data are back in LDS.
+template <int R, bool INV, bool LINES_FAST, int NT, int EPT, typename T>
+__device__ __forceinline__ void lds_stage(cx<T>* buf, const LdsLines& L, int n, int Ns,
+                                          const cx<T>* __restrict__ tw)
+{
+    constexpr int KMAX = (EPT + R - 1) / R;
+    const int nb = n / R;               // butterflies per line
+    const int B = nb * L.nlines;        // butterflies in the tile
+    cx<T> v[KMAX][R];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = (int)threadIdx.x + k * NT;
+        if (b < B) {
+            int j, w;
+            if (LINES_FAST) {
+                w = b % L.nlines;
+                j = b / L.nlines;
+            } else {
+                j = b % nb;
+                w = b / nb;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k][r] = buf[lds_addr(L, w, j + r * nb)];
+            if (Ns > 1) {
+                const int m = j % Ns;
+                const cx<T>* t = tw + m * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[k][r] = twmul<INV, T>(v[k][r], t[r - 1]);
+            }
+            dftR<R, INV, T>(v[k]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = (int)threadIdx.x + k * NT;
+        if (b < B) {
+            int j, w;
+            if (LINES_FAST) {
+                w = b % L.nlines;
+                j = b / L.nlines;
+            } else {
+                j = b % nb;
+                w = b / nb;
+            }
+            const int m = j % Ns;
+            const int base = (j - m) * R + m;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lds_addr(L, w, base + r * Ns)] = v[k][r];
+        }
+    }
+    __syncthreads();
+}
+
+// All stages of one axis.  tw: the axis' stage twiddle table (forward values).
+template <bool INV, bool LINES_FAST, int NT, int EPT, typename T>
+__device__ void lds_fft(cx<T>* buf, const LdsLines& L, const AxisSched& S, const cx<T>* __restrict__ tw)
+{
+    for (int s = 0; s < S.nst; ++s) {
+        const int R = S.radix[s];
+        const int Ns = S.ns[s];
+        const cx<T>* t = tw + S.twoff[s];
+        switch (R) {
+        case 16: lds_stage<16, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
+        case 8: lds_stage<8, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
+        case 4: lds_stage<4, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
+        case 3: lds_stage<3, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
+        case 2: lds_stage<2, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
+        default: break;
+        }
+    }
+}
+
+// ------------------------------------------------- real <-> half-length --
+// Rows are held as H = h+1 slots (h = n2/2).  The forward split turns the
+// length-h DFT Z of z[m] = x[2m] + i x[2m+1] into the bins X[0..h] of the
+// real row; the inverse merge does the reverse.  Each thread owns the pair of
+// slots (k, h-k), so both run in place.
+//   forward: P = (Z[k] + conj Z[h-k]) / 2,  Q = w^k (Z[k] - conj Z[h-k]) / (2i),
+//            X[k] = P + Q,  X[h-k] = conj(P - Q),  X[0] = Re Z0 + Im Z0,
+//            X[h] = Re Z0 - Im Z0  (w = exp(-2 pi i/n2))
+//   inverse: A = X[k] + conj X[h-k],  B = i w^{-k} (X[k] - conj X[h-k]),
+//            Z[k] = A + B,  Z[h-k] = conj(A - B),
+//            Z[0] = (Re X0 + Re Xh) + i (Re X0 - Re Xh)
+//            (the imaginary parts of X[0] and X[h] are never read).
+template <int NT, typename T>
+__device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, int h,
+                                           const cx<T>* __restrict__ post)
+{
+    const int npair = h / 2 + 1;  // k = 0 .. h/2
+    const int total = rows * npair;
+    for (int e = (int)threadIdx.x; e < total; e += NT) {
+        const int q = e / npair;
+        const int k = e - q * npair;
+        cx<T>* Z = buf + q * rstride;
+        if (k == 0) {
+            cx<T> z0 = Z[0];
+            Z[0] = mk<T>(z0.x + z0.y, (T)0);
+            Z[h] = mk<T>(z0.x - z0.y, (T)0);
+        } else {
+            cx<T> a = Z[k], b = Z[h - k];
+            cx<T> P = mk<T>((T)0.5 * (a.x + b.x), (T)0.5 * (a.y - b.y));
+            // (a - conj b) / (2i) = ((a.y + b.y) - i (a.x - b.x)) / 2
+            cx<T> O = mk<T>((T)0.5 * (a.y + b.y), (T)-0.5 * (a.x - b.x));
+            cx<T> Q = cmul<T>(O, post[k]);
+            Z[k] = cadd<T>(P, Q);
+            if (2 * k != h) Z[h - k] = cconj<T>(csub<T>(P, Q));
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int rstride, int h,
+                                           const cx<T>* __restrict__ post)
+{
+    const int npair = h / 2 + 1;
+    const int total = rows * npair;
+    for (int e = (int)threadIdx.x; e < total; e += NT) {
+        const int q = e / npair;
+        const int k = e - q * npair;
+        cx<T>* Z = buf + q * rstride;
+        if (k == 0) {
+            T a0 = Z[0].x, bh = Z[h].x;
+            Z[0] = mk<T>(a0 + bh, a0 - bh);
+        } else {
+            cx<T> a = Z[k], b = Z[h - k];
+            cx<T> A = mk<T>(a.x + b.x, a.y - b.y);
+            cx<T> D = mk<T>(a.x - b.x, a.y + b.y);
+            // i * conj(w^k) * D
+            cx<T> wD = cmulc<T>(D, post[k]);
+            cx<T> Bv = mk<T>(-wD.y, wD.x);
+            Z[k] = cadd<T>(A, Bv);
+            if (2 * k != h) Z[h - k] = cconj<T>(csub<T>(A, Bv));
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace fft3d

@@ -1,0 +1,103 @@
+// fft3d_internal.hpp -- host-side plan of the 3D r2c/c2r library and the
+// kernel launchers it drives.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fft3d_sched.hpp"
+
+namespace fft3d {
+
+// LDS per workgroup on gfx950, and the budget for a tile when two
+// workgroups should share a compute unit.
+constexpr int kLdsMax = 160 * 1024;
+constexpr int kLdsHalf = 80 * 1024;
+
+// Thread counts / elements-per-thread of the two kernel tiers.
+constexpr int kNtSmall = 256;
+constexpr int kNtBig = 512;
+template <typename T> struct Tier;
+template <> struct Tier<float> {
+    static constexpr int kEptSmall = 32;  // 8192 elements, 64 KB
+    static constexpr int kEptBig = 40;    // 20480 elements, 160 KB
+};
+template <> struct Tier<double> {
+    static constexpr int kEptSmall = 16;  // 4096 elements, 64 KB
+    static constexpr int kEptBig = 20;    // 10240 elements, 160 KB
+};
+
+// Strided line pass over an array viewed as nbatch blocks of n rows by ncols
+// columns: element (b, i, c) at b*bstride + i*S + c.  Tiles are W consecutive
+// columns by all n rows of one block.
+struct ColPass {
+    int64_t S = 0;        // row stride (elements)
+    int64_t ncols = 0;    // columns per block
+    int64_t nbatch = 0;   // blocks
+    int64_t bstride = 0;  // block stride (elements)
+    int W = 0;            // tile width (power of two)
+    int wshift = 0;       // log2(W)
+    int64_t tiles_per_batch = 0;
+    bool big = false;     // kernel tier
+    size_t lds = 0;       // dynamic LDS bytes
+};
+
+struct Plan {
+    int64_t n0 = 0, n1 = 0, n2 = 0;
+    int64_t h = 0, H = 0;     // h = n2/2, H = h+1
+    int64_t C = 0;            // n1*H, columns of the n0 pass
+    int64_t M = 0;            // n0*n1*H complex outputs
+    int64_t N = 0;            // n0*n1*n2 real inputs
+    int dtype = 0;            // 0 FP32, 1 FP64
+    int elem = 4;             // bytes per real scalar
+
+    AxisSched ax0{}, ax1{}, ax2h{};  // stage schedules: n0, n1, and h = n2/2
+    // Twiddle table (forward roots of unity) in long double, interleaved re, im;
+    // offsets in complex elements.  Rounded once to the plan's dtype on upload.
+    std::vector<long double> tw_host;
+    int64_t off_ax2h = 0, off_post = 0, off_ax1 = 0, off_ax0 = 0, tw_count = 0;
+
+    // plane step
+    bool fused_plane = false;  // whole n1 x H plane in LDS
+    int ppw = 1;               // planes per workgroup (fused)
+    bool plane_big = false;
+    size_t plane_lds = 0;
+    int rpw = 1;               // rows per workgroup (split)
+    bool rows_big = false;
+    size_t rows_lds = 0;
+    ColPass pass1;             // n1 columns of each plane (split)
+    ColPass pass0;             // n0 columns over C (the strided step)
+
+    // device state
+    bool has_device = false;
+    int device = -1;
+    void* d_tw = nullptr;
+
+    std::string describe() const;
+};
+
+// Build the host part of a plan (schedules, tables, strategy).  Returns an
+// FFT3D_* code; `why` receives a message on failure.
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, std::string& why);
+
+// Factor n = 2^a 3^b into stages; false if n has another prime factor.
+bool make_schedule(int64_t n, AxisSched& s);
+
+// e^{-2 pi i e/m}, quadrant-reduced, in long double.
+void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s);
+
+// Launchers (enqueue on `stream`, no allocation, no synchronisation).
+hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
+hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
+hipError_t launch_cols(const Plan& p, const ColPass& cp, const AxisSched& ax, int64_t tw_off,
+                       const void* in, void* out, bool inverse, hipStream_t stream);
+// Raise the dynamic-LDS limit of every kernel once per process.
+hipError_t kernels_init();
+
+}  // namespace fft3d

@@ -1,0 +1,324 @@
+// fft3d_plan.cpp -- host part of a plan: radix schedules, twiddle tables and
+// the choice of kernels and tile shapes.  Runs once per (shape, dtype).
+#include <math.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/fft3d.h"
+#include "fft3d_internal.hpp"
+
+namespace fft3d {
+
+// ------------------------------------------------------------ schedules --
+
+// n = 2^a 3^b.  The power-of-two part takes ceil(a/4) stages with radices as
+// equal as possible (512 = 8*8*8, 1024 = 16*8*8, 256 = 16*16, 32 = 8*4),
+// followed by one radix-3 stage per factor 3.
+bool make_schedule(int64_t n, AxisSched& s)
+{
+    s = AxisSched{};
+    if (n < 1 || n > (int64_t(1) << 30)) return false;
+    s.n = (int32_t)n;
+    int64_t m = n;
+    int a = 0, b = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++a;
+    }
+    while (m % 3 == 0) {
+        m /= 3;
+        ++b;
+    }
+    if (m != 1) return false;
+    int radices[kMaxStages];
+    int cnt = 0;
+    if (a > 0) {
+        const int s2 = (a + 3) / 4;
+        const int base = a / s2, extra = a % s2;
+        for (int i = 0; i < s2; ++i) {
+            if (cnt >= kMaxStages) return false;
+            radices[cnt++] = 1 << (base + (i < extra ? 1 : 0));
+        }
+    }
+    for (int i = 0; i < b; ++i) {
+        if (cnt >= kMaxStages) return false;
+        radices[cnt++] = 3;
+    }
+    int32_t ns = 1, off = 0;
+    for (int i = 0; i < cnt; ++i) {
+        s.radix[i] = radices[i];
+        s.ns[i] = ns;
+        s.twoff[i] = off;
+        if (ns > 1) off += ns * (radices[i] - 1);
+        ns *= radices[i];
+    }
+    s.nst = cnt;
+    return true;
+}
+
+static int64_t stage_twiddle_count(const AxisSched& s)
+{
+    int64_t c = 0;
+    for (int i = 0; i < s.nst; ++i)
+        if (s.ns[i] > 1) c += (int64_t)s.ns[i] * (s.radix[i] - 1);
+    return c;
+}
+
+// e^{-2 pi i e/m}.  The angle is reduced exactly in integers: 4e = q m + r,
+// angle = (pi/2)(q + r/m); the base angle is folded to [0, pi/4] (sin/cos of
+// at most pi/4), the quadrant q applied by exact sign/swap.  Multiples of
+// pi/2 are exact, odd multiples of pi/4 are sqrt(1/2).
+void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s)
+{
+    const long double HALF_PI = 1.570796326794896619231321691639751442L;
+    e %= m;
+    if (e < 0) e += m;
+    const int64_t q = (4 * e) / m;
+    const int64_t r = (4 * e) % m;
+    long double cb, sb;  // cos, sin of the base angle (pi/2) r/m
+    if (r == 0) {
+        cb = 1.0L;
+        sb = 0.0L;
+    } else if (2 * r == m) {
+        cb = sb = sqrtl(0.5L);
+    } else if (2 * r < m) {
+        long double phi = HALF_PI * (long double)r / (long double)m;
+        cb = cosl(phi);
+        sb = sinl(phi);
+    } else {
+        long double phi = HALF_PI * (long double)(m - r) / (long double)m;
+        cb = sinl(phi);
+        sb = cosl(phi);
+    }
+    long double ct, st;  // cos, sin of the full angle
+    switch (q & 3) {
+    case 0: ct = cb; st = sb; break;
+    case 1: ct = -sb; st = cb; break;
+    case 2: ct = -cb; st = -sb; break;
+    default: ct = sb; st = -cb; break;
+    }
+    *c = ct;
+    *s = -st;  // forward root: exp(-i angle)
+}
+
+static void fill_stage_twiddles(const AxisSched& s, long double* out)
+{
+    for (int i = 0; i < s.nst; ++i) {
+        const int R = s.radix[i], Ns = s.ns[i];
+        if (Ns == 1) continue;
+        long double* t = out + 2 * (int64_t)s.twoff[i];
+        for (int m = 0; m < Ns; ++m)
+            for (int r = 1; r < R; ++r) {
+                long double c, sn;
+                root_of_unity_ld((int64_t)r * m, (int64_t)Ns * R, &c, &sn);
+                t[2 * (m * (R - 1) + (r - 1))] = c;
+                t[2 * (m * (R - 1) + (r - 1)) + 1] = sn;
+            }
+    }
+}
+
+// ------------------------------------------------------------- strategy --
+
+static int ilog2(int v)
+{
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+// Tile width W (columns per tile) for a pass of length-n lines over ncols
+// columns: aim for rows of >= 128 contiguous bytes, widen for short lines so
+// a tile still carries >= 2048 elements, keep within one tier.
+static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64_t nbatch, int64_t bstride,
+                         int cxs, int es, int eb)
+{
+    cp = ColPass{};
+    cp.S = S;
+    cp.ncols = ncols;
+    cp.nbatch = nbatch;
+    cp.bstride = bstride;
+    const int target = std::max(1, 128 / cxs);
+    int64_t cap = 1;
+    while (cap < ncols && cap < 64) cap *= 2;
+    int W = std::min<int64_t>(target, cap);
+    while (W < 64 && W < cap && n * W < 2048 && n * W * 2 <= es) W *= 2;
+    bool big = false;
+    if (n * W > es) {
+        // prefer the big tier at the target width over narrow segments
+        if (n * W <= eb && n * W * cxs <= kLdsMax) {
+            big = true;
+        } else {
+            while (W > 1 && n * W > es) W /= 2;
+            if (n * W > es) {
+                big = true;
+                while (W > 1 && (n * W > eb || n * W * cxs > kLdsMax)) W /= 2;
+                if (n * W > eb || n * W * cxs > kLdsMax) return false;
+            }
+        }
+    }
+    cp.W = W;
+    cp.wshift = ilog2(W);
+    cp.big = big;
+    cp.tiles_per_batch = (ncols + W - 1) / W;
+    cp.lds = (size_t)(n * W * cxs);
+    return true;
+}
+
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, std::string& why)
+{
+    char msg[256];
+    if (n0 < 1 || n1 < 1 || n2 < 1) {
+        why = "extents must be >= 1";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    if (dtype != FFT3D_F32 && dtype != FFT3D_F64) {
+        why = "dtype must be FFT3D_F32 or FFT3D_F64";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    if (n2 % 2 != 0) {
+        snprintf(msg, sizeof msg, "n2 = %lld is odd; the GPU path needs an even n2", (long long)n2);
+        why = msg;
+        return FFT3D_ERR_UNSUPPORTED;
+    }
+    if (n0 > 4096 || n1 > 4096 || n2 > 8192) {
+        why = "extents above n0, n1 <= 4096, n2 <= 8192 are not supported";
+        return FFT3D_ERR_UNSUPPORTED;
+    }
+    p = Plan{};
+    p.n0 = n0;
+    p.n1 = n1;
+    p.n2 = n2;
+    p.h = n2 / 2;
+    p.H = p.h + 1;
+    p.C = n1 * p.H;
+    p.M = n0 * p.C;
+    p.N = n0 * n1 * n2;
+    p.dtype = dtype;
+    p.elem = dtype == FFT3D_F64 ? 8 : 4;
+    if (!make_schedule(n0, p.ax0) || !make_schedule(n1, p.ax1) || !make_schedule(p.h, p.ax2h)) {
+        snprintf(msg, sizeof msg, "extents %lld x %lld x %lld: n0, n1 and n2/2 must have no prime factor other than 2 and 3",
+                 (long long)n0, (long long)n1, (long long)n2);
+        why = msg;
+        return FFT3D_ERR_UNSUPPORTED;
+    }
+
+    // twiddle table: [n2/2 stages | split roots k = 0..h | n1 stages | n0 stages]
+    p.off_ax2h = 0;
+    p.off_post = p.off_ax2h + stage_twiddle_count(p.ax2h);
+    p.off_ax1 = p.off_post + (p.h + 1);
+    p.off_ax0 = p.off_ax1 + stage_twiddle_count(p.ax1);
+    p.tw_count = p.off_ax0 + stage_twiddle_count(p.ax0);
+    p.tw_host.assign(2 * (size_t)p.tw_count, 0.0L);
+    fill_stage_twiddles(p.ax2h, p.tw_host.data() + 2 * p.off_ax2h);
+    for (int64_t k = 0; k <= p.h; ++k) {
+        long double c, s;
+        root_of_unity_ld(k, n2, &c, &s);
+        p.tw_host[2 * (p.off_post + k)] = c;
+        p.tw_host[2 * (p.off_post + k) + 1] = s;
+    }
+    fill_stage_twiddles(p.ax1, p.tw_host.data() + 2 * p.off_ax1);
+    fill_stage_twiddles(p.ax0, p.tw_host.data() + 2 * p.off_ax0);
+
+    // kernel choice
+    const int cxs = 2 * p.elem;
+    const int es = kNtSmall * (dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
+    const int eb = kNtBig * (dtype ? Tier<double>::kEptBig : Tier<float>::kEptBig);
+    const int64_t plane_elems = n1 * p.H;  // >= n1*h: bounds both plane phases
+    const int64_t plane_bytes = plane_elems * cxs;
+    if (plane_elems <= es && plane_bytes <= kLdsHalf) {
+        p.fused_plane = true;
+        p.plane_big = false;
+        p.ppw = 1;
+        p.plane_lds = (size_t)plane_bytes;
+    } else if (plane_elems <= eb && plane_bytes <= kLdsMax) {
+        p.fused_plane = true;
+        p.plane_big = true;
+        p.ppw = 1;
+        p.plane_lds = (size_t)plane_bytes;
+    } else {
+        p.fused_plane = false;
+        int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / (p.H * cxs));
+        p.rows_big = false;
+        if (r < 1) {
+            r = std::min<int64_t>(eb / p.h, kLdsMax / (p.H * cxs));
+            p.rows_big = true;
+        }
+        if (r < 1) {
+            why = "n2 too large for one row in LDS";
+            return FFT3D_ERR_UNSUPPORTED;
+        }
+        p.rpw = (int)std::min<int64_t>(r, n0 * n1);
+        p.rows_lds = (size_t)(p.rpw * p.H * cxs);
+        if (!make_colpass(p.pass1, n1, p.H, p.H, n0, n1 * p.H, cxs, es, eb)) {
+            why = "n1 too large for a column tile";
+            return FFT3D_ERR_UNSUPPORTED;
+        }
+    }
+    if (!make_colpass(p.pass0, n0, p.C, p.C, 1, 0, cxs, es, eb)) {
+        why = "n0 too large for a column tile";
+        return FFT3D_ERR_UNSUPPORTED;
+    }
+    return FFT3D_OK;
+}
+
+// ------------------------------------------------------------- describe --
+
+static std::string sched_json(const AxisSched& s)
+{
+    std::string r = "{\"n\": " + std::to_string(s.n) + ", \"radices\": [";
+    for (int i = 0; i < s.nst; ++i) r += (i ? ", " : "") + std::to_string(s.radix[i]);
+    return r + "]}";
+}
+
+static std::string pass_json(const ColPass& c)
+{
+    char b[320];
+    snprintf(b, sizeof b,
+             "{\"row_stride\": %lld, \"ncols\": %lld, \"nbatch\": %lld, \"batch_stride\": %lld, "
+             "\"W\": %d, \"tier\": \"%s\", \"grid\": %lld, \"lds\": %zu}",
+             (long long)c.S, (long long)c.ncols, (long long)c.nbatch, (long long)c.bstride, c.W,
+             c.big ? "big" : "small", (long long)(c.nbatch * c.tiles_per_batch), c.lds);
+    return b;
+}
+
+std::string Plan::describe() const
+{
+    char b[512];
+    snprintf(b, sizeof b,
+             "{\"n0\": %lld, \"n1\": %lld, \"n2\": %lld, \"dtype\": \"%s\", \"H\": %lld, \"columns\": %lld, "
+             "\"device\": %d, \"twiddles\": %lld, ",
+             (long long)n0, (long long)n1, (long long)n2, dtype ? "f64" : "f32", (long long)H, (long long)C,
+             has_device ? device : -1, (long long)tw_count);
+    std::string r = b;
+    r += "\"schedules\": {\"n0\": " + sched_json(ax0) + ", \"n1\": " + sched_json(ax1) +
+         ", \"n2_half\": " + sched_json(ax2h) + "}, ";
+    if (fused_plane) {
+        snprintf(b, sizeof b,
+                 "\"plane\": {\"kind\": \"fused\", \"planes_per_wg\": %d, \"tier\": \"%s\", \"grid\": %lld, "
+                 "\"lds\": %zu}, ",
+                 ppw, plane_big ? "big" : "small", (long long)((n0 + ppw - 1) / ppw), plane_lds);
+        r += b;
+    } else {
+        snprintf(b, sizeof b,
+                 "\"plane\": {\"kind\": \"split\", \"rows_per_wg\": %d, \"tier\": \"%s\", \"grid\": %lld, "
+                 "\"lds\": %zu, \"n1_pass\": ",
+                 rpw, rows_big ? "big" : "small", (long long)((n0 * n1 + rpw - 1) / rpw), rows_lds);
+        r += b;
+        r += pass_json(pass1) + "}, ";
+    }
+    r += "\"n0_pass\": " + pass_json(pass0) + ", ";
+    // pass lists (FFT3D_PASS_* ids) of the two directions
+    std::string f = "[0", i = "[";
+    if (!fused_plane && n1 > 1) f += ", 1";
+    if (n0 > 1) {
+        f += ", 2";
+        i += "3, ";
+    }
+    if (!fused_plane && n1 > 1) i += "4, ";
+    r += "\"r2c_passes\": " + f + "], \"c2r_passes\": " + i + "5]}";
+    return r;
+}
+
+}  // namespace fft3d

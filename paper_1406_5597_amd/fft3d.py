@@ -1,0 +1,285 @@
+"""Python binding of libfft3d: the C entry points under the same names.
+
+Argument marshalling only -- every step of the transforms runs in the HIP
+kernels of ``libfft3d.so``.  Arrays are torch tensors on the GPU (or raw
+device addresses as ints); streams are torch streams, raw ``hipStream_t``
+ints, or None for torch's current stream.  If the library is not built this
+module raises on import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfft3d.so")
+
+FFT3D_F32 = 0
+FFT3D_F64 = 1
+FFT3D_OK = 0
+FFT3D_ERR_INVALID_ARG = -1
+FFT3D_ERR_UNSUPPORTED = -2
+FFT3D_ERR_NOMEM = -3
+FFT3D_ERR_HIP = -4
+FFT3D_ERR_BUDGET = -5
+FFT3D_ERR_ALIGN = -6
+FFT3D_R2C = 0
+FFT3D_C2R = 1
+FFT3D_ROUNDTRIP = 2
+FFT3D_PLAN_HOST_ONLY = 1
+FFT3D_PASS_PLANE_R2C = 0
+FFT3D_PASS_N1_FWD = 1
+FFT3D_PASS_N0_FWD = 2
+FFT3D_PASS_N0_INV = 3
+FFT3D_PASS_N1_INV = 4
+FFT3D_PASS_PLANE_C2R = 5
+
+# Every symbol include/fft3d.h declares.
+EXPORTS = (
+    "fft3d_version", "fft3d_plan", "fft3d_plan_ex", "fft3d_plan_destroy", "fft3d_work_bytes",
+    "fft3d_real_bytes", "fft3d_complex_bytes", "fft3d_r2c", "fft3d_c2r", "fft3d_batch_submit",
+    "fft3d_strerror", "fft3d_last_error", "fft3d_plan_describe", "fft3d_plan_twiddles",
+    "fft3d_exchange_block", "fft3d_run_pass",
+)
+
+
+class Fft3dError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("dir", ctypes.c_int), ("in_", ctypes.c_void_p),
+                ("mid", ctypes.c_void_p), ("out", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfft3d.so is not built (run `python -m paper_1406_5597_amd.build` "
+                          "or __graft_entry__.build()); there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "fft3d_version": (ctypes.c_int, []),
+        "fft3d_plan": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.POINTER(vp)]),
+        "fft3d_plan_ex": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
+        "fft3d_plan_destroy": (ctypes.c_int, [vp]),
+        "fft3d_work_bytes": (sz, [vp]),
+        "fft3d_real_bytes": (sz, [vp]),
+        "fft3d_complex_bytes": (sz, [vp]),
+        "fft3d_r2c": (ctypes.c_int, [vp, vp, vp, vp]),
+        "fft3d_c2r": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fft3d_batch_submit": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp]),
+        "fft3d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "fft3d_last_error": (ctypes.c_char_p, []),
+        "fft3d_plan_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
+        "fft3d_plan_twiddles": (i64, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64]),
+        "fft3d_exchange_block": (ctypes.c_int, [i64, i64, i64, i64, i64, ctypes.POINTER(i64)]),
+        "fft3d_run_pass": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _strerror(code: int) -> str:
+    return lib.fft3d_strerror(code).decode()
+
+
+def fft3d_last_error() -> str:
+    return lib.fft3d_last_error().decode()
+
+
+def fft3d_strerror(code: int) -> str:
+    return _strerror(code)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise Fft3dError(rc, fft3d_last_error())
+    return rc
+
+
+def _addr(a) -> int:
+    if a is None:
+        return 0
+    if isinstance(a, int):
+        return a
+    return a.data_ptr()
+
+
+def _stream(s) -> int:
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def fft3d_version() -> int:
+    return lib.fft3d_version()
+
+
+class Plan:
+    """An fft3d plan; owns the C handle (destroyed on close / garbage collection)."""
+
+    def __init__(self, n0: int, n1: int, n2: int, dtype: str = "f32", host_only: bool = False):
+        self.shape = (int(n0), int(n1), int(n2))
+        self.dtype = dtype
+        dt = {"f32": FFT3D_F32, "f64": FFT3D_F64}.get(dtype)
+        if dt is None:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        h = ctypes.c_void_p()
+        _check(lib.fft3d_plan_ex(int(n0), int(n1), int(n2), dt, FFT3D_PLAN_HOST_ONLY if host_only else 0,
+                                 ctypes.byref(h)))
+        self.handle = h.value
+
+    @property
+    def half_shape(self):
+        n0, n1, n2 = self.shape
+        return (n0, n1, n2 // 2 + 1)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.fft3d_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def describe(self) -> dict:
+        n = _check(lib.fft3d_plan_describe(self.handle, None, 0))
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.fft3d_plan_describe(self.handle, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def twiddles(self, which: int):
+        import numpy as np
+        n = _check(lib.fft3d_plan_twiddles(self.handle, which, None, 0))
+        out = np.zeros(2 * max(n, 1), dtype=np.float64)
+        lib.fft3d_plan_twiddles(self.handle, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+        return out[: 2 * n].view(np.complex128)
+
+    @property
+    def work_bytes(self) -> int:
+        return lib.fft3d_work_bytes(self.handle)
+
+    @property
+    def real_bytes(self) -> int:
+        return lib.fft3d_real_bytes(self.handle)
+
+    @property
+    def complex_bytes(self) -> int:
+        return lib.fft3d_complex_bytes(self.handle)
+
+
+def fft3d_plan(n0: int, n1: int, n2: int, dtype: str = "f32") -> Plan:
+    return Plan(n0, n1, n2, dtype)
+
+
+def fft3d_plan_ex(n0: int, n1: int, n2: int, dtype: str = "f32", flags: int = 0) -> Plan:
+    return Plan(n0, n1, n2, dtype, host_only=bool(flags & FFT3D_PLAN_HOST_ONLY))
+
+
+def fft3d_plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def fft3d_work_bytes(plan: Plan) -> int:
+    return plan.work_bytes
+
+
+def fft3d_r2c(plan: Plan, x, X, stream=None) -> None:
+    _check(lib.fft3d_r2c(plan.handle, _addr(x), _addr(X), _stream(stream)))
+
+
+def fft3d_c2r(plan: Plan, X, y, work=None, stream=None) -> None:
+    _check(lib.fft3d_c2r(plan.handle, _addr(X), _addr(y), _addr(work), _stream(stream)))
+
+
+def fft3d_batch_submit(items, stream=None) -> None:
+    """items: sequence of (plan, dir, in, mid, out, work) tuples."""
+    arr = (BatchItem * max(len(items), 1))()
+    for i, (plan, d, a, m, o, w) in enumerate(items):
+        arr[i] = BatchItem(plan.handle, d, _addr(a), _addr(m), _addr(o), _addr(w))
+    _check(lib.fft3d_batch_submit(arr, len(items), _stream(stream)))
+
+
+def fft3d_run_pass(plan: Plan, pass_id: int, src, dst, stream=None) -> None:
+    _check(lib.fft3d_run_pass(plan.handle, pass_id, _addr(src), _addr(dst), _stream(stream)))
+
+
+def fft3d_plan_describe(plan: Plan) -> dict:
+    return plan.describe()
+
+
+def fft3d_plan_twiddles(plan: Plan, which: int):
+    return plan.twiddles(which)
+
+
+def fft3d_exchange_block(n0: int, ncols: int, p: int, src: int, dst: int):
+    """(sender first, count, blocklen, stride), (receiver first, count, blocklen, stride)."""
+    out = (ctypes.c_int64 * 8)()
+    _check(lib.fft3d_exchange_block(n0, ncols, p, src, dst, out))
+    v = list(out)
+    return tuple(v[:4]), tuple(v[4:])
+
+
+# ------------------------------------------------------------ conveniences --
+
+def torch_dtypes(dtype: str):
+    import torch
+    return (torch.float32, torch.complex64) if dtype == "f32" else (torch.float64, torch.complex128)
+
+
+def empty_real(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty(plan.shape, dtype=torch_dtypes(plan.dtype)[0], device=device)
+
+
+def empty_complex(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty(plan.half_shape, dtype=torch_dtypes(plan.dtype)[1], device=device)
+
+
+def r2c(plan: Plan, x, X=None, stream=None):
+    """Forward transform of the real GPU tensor x; returns X (allocated if None)."""
+    if X is None:
+        X = empty_complex(plan, x.device)
+    _shape_check(plan, x, X)
+    fft3d_r2c(plan, x, X, stream)
+    return X
+
+
+def c2r(plan: Plan, X, y=None, work=None, stream=None):
+    """Inverse transform; X is preserved iff work is given."""
+    if y is None:
+        y = empty_real(plan, X.device)
+    _shape_check(plan, y, X)
+    fft3d_c2r(plan, X, y, work, stream)
+    return y
+
+
+def _shape_check(plan: Plan, real, cplx) -> None:
+    rd, cd = torch_dtypes(plan.dtype)
+    if tuple(real.shape) != plan.shape or real.dtype != rd or not real.is_contiguous():
+        raise ValueError("real array must be a contiguous %s tensor of shape %s" % (rd, plan.shape))
+    if tuple(cplx.shape) != plan.half_shape or cplx.dtype != cd or not cplx.is_contiguous():
+        raise ValueError("complex array must be a contiguous %s tensor of shape %s" % (cd, plan.half_shape))

@@ -1,0 +1,217 @@
+"""Host-side tests of libfft3d: no GPU needed.
+
+The library loads and exports every symbol include/fft3d.h declares; plan
+validation and error codes; radix schedules; twiddle tables against long
+double roots of unity; the slab-exchange map against the paper's worked
+example (Sec. 2.2, Fig. 3).
+"""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1406_5597_amd import fft3d
+    return fft3d
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "fft3d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft3d_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(F):
+    syms = header_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(F.lib, s), s
+    assert sorted(F.EXPORTS) == syms
+    assert F.fft3d_version() >= 100
+
+
+def test_binding_has_no_fallback():
+    # the binding refuses to import without the built library
+    src = open(os.path.join(ROOT, "paper_1406_5597_amd", "fft3d.py")).read()
+    assert "oracle" not in src
+    assert "numpy.fft" not in src and "torch.fft" not in src
+
+
+@pytest.mark.parametrize("shape,dtype,code", [
+    ((0, 4, 4), "f32", -1), ((4, -1, 4), "f64", -1), ((4, 4, 0), "f32", -1),
+    ((5, 4, 4), "f32", -2), ((4, 7, 4), "f64", -2), ((4, 4, 10), "f32", -2),
+    ((4, 4, 5), "f32", -2), ((4, 4, 7), "f64", -2), ((8192, 4, 4), "f32", -2),
+    ((4, 4, 16384), "f32", -2),
+])
+def test_plan_rejects(F, shape, dtype, code):
+    with pytest.raises(F.Fft3dError) as e:
+        F.Plan(*shape, dtype=dtype, host_only=True)
+    assert e.value.code == code
+    assert F.fft3d_last_error()
+
+
+def test_plan_bad_dtype_and_null_out(F):
+    h = ctypes.c_void_p()
+    assert F.lib.fft3d_plan_ex(4, 4, 4, 7, F.FFT3D_PLAN_HOST_ONLY, ctypes.byref(h)) == -1
+    assert F.lib.fft3d_plan_ex(4, 4, 4, 0, F.FFT3D_PLAN_HOST_ONLY, None) == -1
+    assert F.lib.fft3d_plan_ex(4, 4, 4, 0, 8, ctypes.byref(h)) == -1
+
+
+def test_host_only_plan_cannot_execute(F):
+    p = F.Plan(8, 8, 8, "f32", host_only=True)
+    assert F.lib.fft3d_r2c(p.handle, 256, 4096, None) == -1
+    assert "host-only" in F.fft3d_last_error()
+    assert F.lib.fft3d_r2c(None, 256, 4096, None) == -1
+    assert F.lib.fft3d_c2r(None, 256, 4096, None, None) == -1
+
+
+def test_strerror_and_sizes(F):
+    for c in (0, -1, -2, -3, -4, -5, -6):
+        assert F.fft3d_strerror(c) != "unknown error code"
+    assert F.fft3d_strerror(-99) == "unknown error code"
+    p = F.Plan(6, 8, 12, "f64", host_only=True)
+    assert p.real_bytes == 6 * 8 * 12 * 8
+    assert p.complex_bytes == 6 * 8 * 7 * 16 == p.work_bytes
+    q = F.Plan(6, 8, 12, "f32", host_only=True)
+    assert q.work_bytes == 6 * 8 * 7 * 8
+
+
+def test_batch_submit_all_or_nothing(F):
+    p = F.Plan(8, 8, 8, "f32", host_only=True)
+    items = [(p, F.FFT3D_R2C, 256, 0, 4096, 0)]
+    with pytest.raises(F.Fft3dError) as e:
+        F.fft3d_batch_submit(items, stream=0)
+    assert "item 0" in str(e.value)
+    with pytest.raises(F.Fft3dError):
+        F.fft3d_batch_submit([(p, 9, 256, 0, 4096, 0)], stream=0)
+
+
+def smooth23(limit):
+    return sorted(2 ** a * 3 ** b for a in range(13) for b in range(8) if 2 ** a * 3 ** b <= limit)
+
+
+def test_schedules_factor_every_length(F):
+    for n in smooth23(4096):
+        p = F.Plan(n, 1, 2, "f32", host_only=True)
+        rad = p.describe()["schedules"]["n0"]["radices"]
+        assert int(np.prod(rad)) == n if n > 1 else rad == []
+        assert all(r in (2, 3, 4, 8, 16) for r in rad)
+        # the power-of-two part takes the fewest stages of radix <= 16
+        a = (n & -n).bit_length() - 1
+        assert sum(1 for r in rad if r != 3) == (a + 3) // 4
+
+
+_PI50 = None
+
+
+def _root(e, m):
+    """exp(-2 pi i e/m) to 50 significant digits (Decimal Taylor series on the
+    exactly reduced angle), returned as two Decimals."""
+    from decimal import Decimal, getcontext
+    global _PI50
+    getcontext().prec = 60
+    if _PI50 is None:
+        _PI50 = Decimal("3.14159265358979323846264338327950288419716939937510582097494459")
+    e %= m
+    if (4 * e) % m == 0:  # quarter turns are exact: (1,0), (0,-1), (-1,0), (0,1)
+        q = (4 * e) // m
+        return Decimal((1, 0, -1, 0)[q]), Decimal((0, -1, 0, 1)[q])
+    x = 2 * _PI50 * Decimal(e) / Decimal(m)
+
+    def series(t, k):
+        tot = Decimal(0)
+        while abs(t) > Decimal(10) ** -55:
+            tot += t
+            t = -t * x * x / ((k + 1) * (k + 2))
+            k += 2
+        return tot
+
+    return series(Decimal(1), 0), -series(x, 1)
+
+
+def _rounded(v, ft):
+    """Correctly rounded value of the Decimal v in the float type ft."""
+    f = float(v)  # correctly rounded to double
+    if ft is np.float64:
+        return f
+    g = float(np.float32(f))
+    # double rounding can only bite exactly at a float32 midpoint; check it
+    lo, hi = np.nextafter(np.float32(g), np.float32(-2)), np.nextafter(np.float32(g), np.float32(2))
+    from decimal import Decimal
+    best = min((abs(Decimal(float(c)) - v), float(c)) for c in (lo, np.float32(g), hi))
+    return best[1]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(512, 96, 1024), (192, 48, 24), (16, 12, 6), (1024, 1024, 2)])
+def test_twiddle_tables(F, dtype, shape):
+    p = F.Plan(*shape, dtype=dtype, host_only=True)
+    d = p.describe()
+    ft = np.float32 if dtype == "f32" else np.float64
+    eps = np.finfo(ft).eps
+    for which, key in ((0, "n0"), (1, "n1"), (2, "n2_half")):
+        rad = d["schedules"][key]["radices"]
+        tab = p.twiddles(which)
+        k = 0
+        ns = 1
+        for R in rad:
+            if ns > 1:
+                for m in range(ns):
+                    for r in range(1, R):
+                        c, s = _root(r * m, ns * R)
+                        got = tab[k]
+                        # correctly rounded to the plan's dtype
+                        assert got.real == _rounded(c, ft) and got.imag == _rounded(s, ft), (which, R, ns, m, r)
+                        k += 1
+            ns *= R
+        assert k == len(tab)
+    # split roots exp(-2 pi i k/n2), k = 0..n2/2, with exact special angles
+    n2 = shape[2]
+    post = p.twiddles(3)
+    assert len(post) == n2 // 2 + 1
+    assert post[0] == 1 + 0j
+    if n2 % 4 == 0:
+        assert post[n2 // 4] == -1j
+    if n2 % 8 == 0:
+        r = float(ft(np.sqrt(np.longdouble(0.5))))
+        assert post[n2 // 8] == complex(r, -r)
+    for kk in range(len(post)):
+        c, s = _root(kk, n2)
+        assert post[kk].real == _rounded(c, ft) and post[kk].imag == _rounded(s, ft), kk
+
+
+def test_exchange_block_matches_worked_example(F):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "exchange_4x4.json")))
+    n0, ncols, P = g["n0"], g["columns"], g["processes"]
+    A = np.arange(1, n0 * ncols + 1).reshape(n0, ncols)
+    rows = n0 // P
+    slabs = [A[q * rows:(q + 1) * rows].ravel() for q in range(P)]
+    owned = {q: [] for q in range(P)}
+    col_slab = {q: np.zeros(n0 * (ncols // P), dtype=int) for q in range(P)}
+    for src in range(P):
+        for dst in range(P):
+            (f, cnt, bl, st), (rf, rc, rbl, rst) = F.fft3d_exchange_block(n0, ncols, P, src, dst)
+            block = [slabs[src][f + i * st + j] for i in range(cnt) for j in range(bl)]
+            if src != dst:
+                assert block == g["sent"]["%d->%d" % (src, dst)]
+            for i in range(rc):
+                for j in range(rbl):
+                    col_slab[dst][rf + i * rst + j] = slabs[src][f + i * st + j]
+    for q in range(P):
+        assert col_slab[q].tolist() == g["owned_after_exchange"][str(q)]
+        # the received slab is the natural-order column block: no transpose
+        assert col_slab[q].tolist() == A[:, q * (ncols // P):(q + 1) * (ncols // P)].ravel().tolist()
+
+
+def test_exchange_block_rejects(F):
+    with pytest.raises(F.Fft3dError):
+        F.fft3d_exchange_block(6, 4, 4, 0, 1)
+    with pytest.raises(F.Fft3dError):
+        F.fft3d_exchange_block(4, 4, 2, 2, 0)
