@@ -64,8 +64,8 @@ def pair_bytes_min(shape, elem: int) -> int:
     return 2 * (elem * N + 2 * elem * M)
 
 
-def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields):
-    plan = F.Plan(*shape, dtype=dtype)
+def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, split_plane=False):
+    plan = F.Plan(*shape, dtype=dtype, split_plane=split_plane)
     desc = plan.describe()
     elem = 4 if dtype == "f32" else 8
     x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
@@ -138,7 +138,8 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields):
                      "unit": "GB/s", "frac": kern[PASS_NAMES[dom]]["frac"], "traffic": None,
                      "kernel": PASS_NAMES[dom], "alg_bytes_per_launch": pass_bytes(dom, shape, elem),
                      "avg_us": kern[PASS_NAMES[dom]]["avg_us"]},
-        "plan": {"plane": desc["plane"]["kind"], "n0_W": desc["n0_pass"]["W"]},
+        "plan": {"plane": desc["plane"]["kind"], "n0_W": desc["n0_pass"]["W"],
+                 "coop": desc["plane"].get("coop")},
     }
     # one more pair for the accuracy check against the oracle sample
     pair()
@@ -172,6 +173,8 @@ def main() -> int:
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split-plane", action="store_true",
+                    help="two-kernel plane step for large planes instead of the cooperative one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU form (the slab exchange "
@@ -193,7 +196,8 @@ def main() -> int:
     results, keep = {}, {}
     for d in dtypes:
         print("# timing %s ..." % d, file=sys.stderr, flush=True)
-        results[d], keep[d] = run_dtype(F, torch, x64, shape, d, args.steps, args.warmup, fields)
+        results[d], keep[d] = run_dtype(F, torch, x64, shape, d, args.steps, args.warmup, fields,
+                                        args.split_plane)
         print("# %s: %.3f ms/pair, %.1f pairs/s, dominant %s %.1f GB/s" % (
             d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
             results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)
@@ -246,6 +250,7 @@ def main() -> int:
         "gflops": round(r["gflops"], 1),
         "kernels": r["kernels"],
         "roofline": r["roofline"],
+        "plan": r["plan"],
         "cpu_baseline": cpu,
         "copy_GB_s": round(copy_gbs, 1),
     }

@@ -35,7 +35,11 @@
  *     not synchronise: they enqueue kernels on the given stream and return;
  *   - a plan is immutable after creation and may be used from several
  *     streams or host threads at once, as long as every concurrent call has
- *     its own output and work buffers;
+ *     its own output and work buffers -- except a plan whose plane step is
+ *     cooperative (fft3d_plan_describe reports plane.kind "coop": planes
+ *     larger than LDS): it owns a small device counter block, so its calls
+ *     must not overlap in time (issue them on one stream, or order them with
+ *     events; use one plan per concurrently used stream);
  *   - a plan belongs to the device that was current when it was created;
  *     calls must be made with that device current.
  *
@@ -75,7 +79,12 @@ enum {
 enum { FFT3D_R2C = 0, FFT3D_C2R = 1, FFT3D_ROUNDTRIP = 2 };
 
 /* Plan flags for fft3d_plan_ex. */
-enum { FFT3D_PLAN_HOST_ONLY = 1 /* build schedules/tables on the host only; cannot execute */ };
+enum {
+    FFT3D_PLAN_HOST_ONLY = 1,  /* build schedules/tables on the host only; cannot execute */
+    FFT3D_PLAN_SPLIT_PLANE = 2 /* planes larger than LDS: rows kernel + n1 column kernel
+                                  (two sweeps of HBM) instead of the default cooperative
+                                  one-launch plane step */
+};
 
 /* Library version (major*10000 + minor*100 + patch). */
 int fft3d_version(void);
@@ -90,8 +99,10 @@ int fft3d_version(void);
  * On success *out receives the plan. */
 int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out);
 
-/* As fft3d_plan; flags = FFT3D_PLAN_HOST_ONLY builds no device state (usable
- * for fft3d_plan_describe / fft3d_plan_twiddles, not for transforms). */
+/* As fft3d_plan, with flags: FFT3D_PLAN_HOST_ONLY builds no device state
+ * (usable for fft3d_plan_describe / fft3d_plan_twiddles, not for transforms);
+ * FFT3D_PLAN_SPLIT_PLANE selects the two-kernel plane step for large planes.
+ * The cooperative plane step allocates its counter block (a few KB) here. */
 int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out);
 
 /* Free a plan and its device table.  NULL is accepted.  The caller must make
@@ -139,10 +150,12 @@ int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream)
 
 /* The passes a transform is made of, for fft3d_run_pass.  The forward
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
- * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan is
- * "fused" when a whole n1 x (n2/2+1) plane fits in LDS (the plane pass then
- * does both in-plane axes) and "split" otherwise; fft3d_plan_describe reports
- * which, and the pass lists of both directions. */
+ * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan's
+ * plane step is "fused" when a whole n1 x (n2/2+1) plane fits in LDS (one
+ * kernel does both in-plane axes), "coop" for larger planes (one cooperative
+ * launch does both), and "split" with FFT3D_PLAN_SPLIT_PLANE (rows kernel +
+ * N1 pass); fft3d_plan_describe reports which, and the pass lists of both
+ * directions. */
 enum {
     FFT3D_PASS_PLANE_R2C = 0, /* in: real x; out: spectrum (after the plane step) */
     FFT3D_PASS_N1_FWD = 1,    /* in/out: spectrum (in == out allowed) */

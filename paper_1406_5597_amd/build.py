@@ -26,11 +26,15 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
                 "-I" + INCLUDE]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "--offload-arch=" + ARCH, "--cuda-host-only", "-I" + INCLUDE]
 
 SOURCES = [
-    ("fft3d_kernels.hip", DEVICE_FLAGS),
+    ("fft3d_coop_f32.hip", DEVICE_FLAGS),
+    ("fft3d_coop_f64.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f32.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f64.hip", DEVICE_FLAGS),
     ("fft3d_plan.cpp", HOST_FLAGS),
+    ("fft3d_dispatch.cpp", HOST_FLAGS),
     ("fft3d_abi.cpp", HOST_FLAGS),
 ]
 

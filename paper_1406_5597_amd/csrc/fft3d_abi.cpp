@@ -112,16 +112,21 @@ int enqueue_r2c(const fft3d::Plan& p, const void* x, void* X, hipStream_t s)
     if (p.fused_plane) {
         e = fft3d::launch_plane_r2c(p, x, X, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c plane kernel");
+    } else if (p.coop) {
+        e = fft3d::launch_plane_coop(p, x, X, false, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c cooperative plane kernel");
     } else {
-        e = fft3d::launch_rows_r2c(p, x, X, s);
+        e = fft3d::launch_rows_r2c(p, x, X, 0, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
         if (p.n1 > 1) {
-            e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, X, X, false, s);
+            // each XCD walks its chunk of planes backwards: the planes the rows
+            // kernel wrote last are the most likely to be still cached
+            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, X, X, false, 1, s);
             if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
         }
     }
     if (p.n0 > 1) {
-        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, X, X, false, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, X, X, false, 0, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n0 columns kernel");
     }
     return FFT3D_OK;
@@ -135,20 +140,30 @@ int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t 
     void* scratch = work ? work : X;
     const void* cur = X;
     if (p.n0 > 1) {
-        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, cur, scratch, true, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, cur, scratch, true, 0, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n0 columns kernel");
         cur = scratch;
     }
     if (p.fused_plane) {
         e = fft3d::launch_plane_c2r(p, cur, y, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r plane kernel");
+    } else if (p.coop) {
+        // the cooperative kernel transforms the n1 columns in place: with
+        // work, first bring the spectrum there if the n0 pass did not
+        if (cur == X && work) {
+            e = hipMemcpyAsync(work, X, cplx_bytes(p), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r copy to work");
+            cur = work;
+        }
+        e = fft3d::launch_plane_coop(p, cur, y, true, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r cooperative plane kernel");
     } else {
         if (p.n1 > 1) {
-            e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, cur, scratch, true, s);
+            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, cur, scratch, true, 1, s);
             if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
             cur = scratch;
         }
-        e = fft3d::launch_rows_c2r(p, cur, y, s);
+        e = fft3d::launch_rows_c2r(p, cur, y, 0, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
     }
     return FFT3D_OK;
@@ -170,11 +185,12 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
 {
     if (!out) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: out is NULL");
     *out = nullptr;
-    if (flags & ~FFT3D_PLAN_HOST_ONLY) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: unknown flags");
+    if (flags & ~(FFT3D_PLAN_HOST_ONLY | FFT3D_PLAN_SPLIT_PLANE))
+        return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: unknown flags");
     fft3d_plan_s* h = new (std::nothrow) fft3d_plan_s;
     if (!h) return fail(FFT3D_ERR_NOMEM, "fft3d_plan: out of host memory");
     std::string why;
-    int rc = fft3d::plan_build_host(h->p, n0, n1, n2, dtype, why);
+    int rc = fft3d::plan_build_host(h->p, n0, n1, n2, dtype, flags, why);
     if (rc) {
         delete h;
         return fail(rc, "fft3d_plan: " + why);
@@ -220,6 +236,22 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
         h->p.d_tw = d;
         h->p.device = dev;
         h->p.has_device = true;
+        const fft3d::AxisSched sched[3] = {p.ax0, p.ax1, p.ax2h};
+        e = hipMalloc(&h->p.d_sched, sizeof sched);
+        if (e != hipSuccess) {
+            fft3d_plan_destroy(h);
+            return fail(FFT3D_ERR_NOMEM, std::string("fft3d_plan: hipMalloc of schedules: ") + hipGetErrorString(e));
+        }
+        e = hipMemcpy(h->p.d_sched, sched, sizeof sched, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            fft3d_plan_destroy(h);
+            return hip_fail(e, "fft3d_plan: schedule upload");
+        }
+        e = fft3d::coop_setup(h->p);
+        if (e != hipSuccess) {
+            fft3d_plan_destroy(h);
+            return hip_fail(e, "fft3d_plan: cooperative plane step set-up");
+        }
     }
     *out = h;
     return FFT3D_OK;
@@ -236,6 +268,14 @@ int fft3d_plan_destroy(fft3d_plan_t h)
     int rc = FFT3D_OK;
     if (h->p.d_tw) {
         hipError_t e = hipFree(h->p.d_tw);
+        if (e != hipSuccess) rc = hip_fail(e, "fft3d_plan_destroy");
+    }
+    if (h->p.d_ctr) {
+        hipError_t e = hipFree(h->p.d_ctr);
+        if (e != hipSuccess) rc = hip_fail(e, "fft3d_plan_destroy");
+    }
+    if (h->p.d_sched) {
+        hipError_t e = hipFree(h->p.d_sched);
         if (e != hipSuccess) rc = hip_fail(e, "fft3d_plan_destroy");
     }
     delete h;
@@ -312,25 +352,31 @@ int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStrea
     switch (pass) {
     case FFT3D_PASS_PLANE_R2C:
         if (overlaps(in, rb, out, cb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
-        e = p.fused_plane ? fft3d::launch_plane_r2c(p, in, out, s) : fft3d::launch_rows_r2c(p, in, out, s);
+        e = p.fused_plane ? fft3d::launch_plane_r2c(p, in, out, s)
+            : p.coop      ? fft3d::launch_plane_coop(p, in, out, false, s)
+                          : fft3d::launch_rows_r2c(p, in, out, 0, s);
         break;
     case FFT3D_PASS_PLANE_C2R:
+        // the cooperative plane c2r transforms the n1 columns of `in` in place
         if (overlaps(in, cb, out, rb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
-        e = p.fused_plane ? fft3d::launch_plane_c2r(p, in, out, s) : fft3d::launch_rows_c2r(p, in, out, s);
+        e = p.fused_plane ? fft3d::launch_plane_c2r(p, in, out, s)
+            : p.coop      ? fft3d::launch_plane_coop(p, in, out, true, s)
+                          : fft3d::launch_rows_c2r(p, in, out, 0, s);
         break;
     case FFT3D_PASS_N1_FWD:
     case FFT3D_PASS_N1_INV:
-        if (p.fused_plane || p.n1 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n1 pass");
+        if (p.fused_plane || p.coop || p.n1 == 1)
+            return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n1 pass");
         if (in != out && overlaps(in, cb, out, cb))
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
-        e = fft3d::launch_cols(p, p.pass1, p.ax1, p.off_ax1, in, out, pass == FFT3D_PASS_N1_INV, s);
+        e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, in, out, pass == FFT3D_PASS_N1_INV, 1, s);
         break;
     case FFT3D_PASS_N0_FWD:
     case FFT3D_PASS_N0_INV:
         if (p.n0 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n0 pass");
         if (in != out && overlaps(in, cb, out, cb))
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
-        e = fft3d::launch_cols(p, p.pass0, p.ax0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV, 0, s);
         break;
     default: return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: unknown pass");
     }

@@ -176,41 +176,233 @@ template <int R, bool INV, typename T> __device__ __forceinline__ void dftR(cx<T
     else if constexpr (R == 16) dft16<INV, T>(v);
 }
 
+// n / d for n * d < 2^32, with mg = div_magic(d) (0 for d == 1).
+__device__ __forceinline__ int fdiv(int n, uint32_t mg)
+{
+    return mg ? (int)__umulhi((uint32_t)n, mg) : n;
+}
+
 __device__ __forceinline__ int lds_addr(const LdsLines& L, int w, int i)
 {
     if (L.lpp >= L.nlines) return w * L.sw + i * L.si;  // one panel (uniform branch)
-    int p = w / L.lpp;
-    int q = w - p * L.lpp;
+    const int p = fdiv(w, L.mg_lpp);
+    const int q = w - p * L.lpp;
     return p * L.sp + q * L.sw + i * L.si;
 }
 
-// One Stockham stage of radix R over all lines in LDS.  EPT: the largest
-// number of elements (lines * n) per thread the caller will ever pass.
-// Ends with a barrier; the data are back in LDS.
-template <int R, bool INV, bool LINES_FAST, int NT, int EPT, typename T>
-__device__ __forceinline__ void lds_stage(cx<T>* buf, const LdsLines& L, int n, int Ns,
-                                          const cx<T>* __restrict__ tw)
+// ----------------------------------------------------- XCD-aware order --
+// The hardware hands workgroup b to XCD (b mod 8).  xcd_tile maps workgroup b
+// of a G-workgroup grid to a logical tile so that every XCD works through one
+// contiguous chunk of tiles: neighbouring tiles (which share cache lines at
+// their edges) meet in the same L2.  A bijection on [0, G) for any G; with
+// `reverse`, each chunk is walked from its end (the most recently written
+// data first, when the previous pass wrote the chunks in order).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G, bool reverse)
+{
+    const int64_t x = b % kXcds, k = b / kXcds;
+    const int64_t q = G / kXcds, r = G % kXcds;
+    const int64_t len = q + (x < r ? 1 : 0);
+    const int64_t start = x * q + (x < r ? x : r);
+    return start + (reverse ? len - 1 - k : k);
+}
+
+// ------------------------------------------------------ line accessors --
+// A stage addresses element i of line w through a position: at(w, i) gives
+// the position of that element, adv(p, d) the position d elements further
+// along the same line (d is uniform across the workgroup, so the stride
+// arithmetic stays scalar), get/put read and write at a position.  kLds tells
+// the stage driver whether the accessor is the LDS tile (which decides where
+// barriers are needed).
+
+template <typename T> struct LdsIO {
+    static constexpr bool kLds = true;
+    using Pos = int;
+    cx<T>* buf;
+    LdsLines L;
+    __device__ __forceinline__ Pos at(int w, int i) const { return lds_addr(L, w, i); }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const { return p + d * L.si; }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return buf[p]; }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const { buf[p] = v; }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// Device-scope loads: they miss the CU's L1 and read the XCD's L2.  Used for
+// data that another CU of the same XCD wrote earlier in the same kernel (the
+// writer drained its stores to L2 before signalling).
+__device__ __forceinline__ float2 load_l2(const float2* p)
+{
+    const uint64_t u = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float2*>(p)), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, u);
+}
+__device__ __forceinline__ double2 load_l2(const double2* p)
+{
+    uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<double2*>(p));
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double2 r;
+    r.x = __builtin_bit_cast(double, a);
+    r.y = __builtin_bit_cast(double, b);
+    return r;
+}
+// Cache policies of global accesses.  Loads: plain; LD_L2 (device scope,
+// misses L1, see load_l2); LD_STREAM (non-temporal: data read once, kept out
+// of the way of data the cache should hold).  Stores: plain; ST_STREAM
+// (non-temporal: data not read again soon).
+enum { LD_PLAIN = 0, LD_L2 = 1, LD_STREAM = 2 };
+enum { ST_PLAIN = 0, ST_STREAM = 1 };
+
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+template <typename T> struct native2;
+template <> struct native2<float> { using type = f2v_t; };
+template <> struct native2<double> { using type = d2v_t; };
+
+template <int LP, typename T> __device__ __forceinline__ cx<T> load_cx(const cx<T>* p)
+{
+    if constexpr (LP == LD_L2) {
+        return load_l2(p);
+    } else if constexpr (LP == LD_STREAM) {
+        using V = typename native2<T>::type;
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+        return mk<T>(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
+template <int SP, typename T> __device__ __forceinline__ void store_cx(cx<T>* p, cx<T> v)
+{
+    if constexpr (SP == ST_STREAM) {
+        using V = typename native2<T>::type;
+        V w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+    } else {
+        *p = v;
+    }
+}
+
+// W consecutive columns of a row-major block: line w = column w (only the
+// first `width` exist; the others read as zero and are not written),
+// element i = row i at stride S.  src and dst may be equal.  LP / SP: cache
+// policies of the loads and stores.
+template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct ColTileIO {
+    static constexpr bool kLds = false;
+    struct Pos {
+        int64_t off;  // element offset, column clamped to a valid one
+        bool ok;      // the column exists
+    };
+    const cx<T>* src;
+    cx<T>* dst;
+    int64_t S;
+    int width;
+    __device__ __forceinline__ Pos at(int w, int i) const
+    {
+        Pos p;
+        p.ok = w < width;
+        p.off = (int64_t)i * S + (p.ok ? w : width - 1);
+        return p;
+    }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const
+    {
+        p.off += (int64_t)d * S;
+        return p;
+    }
+    // always a valid address (clamped column), then masked
+    __device__ __forceinline__ cx<T> get(Pos p) const
+    {
+        const cx<T> v = load_cx<LP, T>(src + p.off);
+        return p.ok ? v : mk<T>((T)0, (T)0);
+    }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const
+    {
+        if (p.ok) store_cx<SP, T>(dst + p.off, v);
+    }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// Contiguous lines of `len` elements: line q, element i at q*len + i.
+template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct RowsIO {
+    static constexpr bool kLds = false;
+    using Pos = int;
+    const cx<T>* src;
+    cx<T>* dst;
+    int len;
+    __device__ __forceinline__ Pos at(int q, int i) const { return q * len + i; }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const { return p + d; }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return load_cx<LP, T>(src + p); }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const { store_cx<SP, T>(dst + p, v); }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// Whole n1 x H planes, contiguous: line w = column (w mod H) of plane
+// (w div H), element i = row i (stride H).
+template <typename T> struct PlaneColsIO {
+    static constexpr bool kLds = false;
+    using Pos = int;
+    const cx<T>* src;
+    cx<T>* dst;
+    int H;
+    int plane;     // n1 * H
+    uint32_t mgH;  // div_magic(H)
+    __device__ __forceinline__ Pos at(int w, int i) const
+    {
+        const int p = fdiv(w, mgH);
+        return p * plane + (w - p * H) + i * H;
+    }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const { return p + d * H; }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return src[p]; }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const { dst[p] = v; }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// Per-stage constants for stage().
+struct StageArg {
+    int n, nlines, Ns;
+    uint32_t mg_lines, mg_nb, mg_ns;
+};
+
+template <int R, bool LINES_FAST>
+__device__ __forceinline__ void butterfly_of(int b, const StageArg& a, int& j, int& w)
+{
+    if (LINES_FAST) {
+        j = fdiv(b, a.mg_lines);
+        w = b - j * a.nlines;
+    } else {
+        w = fdiv(b, a.mg_nb);
+        j = b - w * (a.n / R);
+    }
+}
+
+template <int R, bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In,
+          class Out>
+__device__ __forceinline__ void stage(const In& in, const Out& out, const StageArg& a,
+                                      const cx<T>* __restrict__ tw)
 {
     constexpr int KMAX = (EPT + R - 1) / R;
-    const int nb = n / R;               // butterflies per line
-    const int B = nb * L.nlines;        // butterflies in the tile
+    const int nb = a.n / R;         // butterflies per line
+    const int B = nb * a.nlines;    // butterflies in the tile
+    const int Ns = a.Ns;
     cx<T> v[KMAX][R];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int b = (int)threadIdx.x + k * NT;
         if (b < B) {
             int j, w;
-            if (LINES_FAST) {
-                w = b % L.nlines;
-                j = b / L.nlines;
-            } else {
-                j = b % nb;
-                w = b / nb;
-            }
+            butterfly_of<R, LINES_FAST>(b, a, j, w);
+            const auto p0 = in.at(w, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[k][r] = buf[lds_addr(L, w, j + r * nb)];
+            for (int r = 0; r < R; ++r) v[k][r] = in.get(in.adv(p0, r * nb));
             if (Ns > 1) {
-                const int m = j % Ns;
+                const int m = j - fdiv(j, a.mg_ns) * Ns;
                 const cx<T>* t = tw + m * (R - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[k][r] = twmul<INV, T>(v[k][r], t[r - 1]);
@@ -218,45 +410,74 @@ __device__ __forceinline__ void lds_stage(cx<T>* buf, const LdsLines& L, int n, 
             dftR<R, INV, T>(v[k]);
         }
     }
-    __syncthreads();
+    if (MID) __syncthreads();
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int b = (int)threadIdx.x + k * NT;
         if (b < B) {
             int j, w;
-            if (LINES_FAST) {
-                w = b % L.nlines;
-                j = b / L.nlines;
-            } else {
-                j = b % nb;
-                w = b / nb;
-            }
-            const int m = j % Ns;
+            butterfly_of<R, LINES_FAST>(b, a, j, w);
+            const int m = j - fdiv(j, a.mg_ns) * Ns;
             const int base = (j - m) * R + m;
+            const auto q0 = out.at(w, base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lds_addr(L, w, base + r * Ns)] = v[k][r];
+            for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[k][r]);
         }
     }
-    __syncthreads();
+    if (END) __syncthreads();
 }
 
-// All stages of one axis.  tw: the axis' stage twiddle table (forward values).
-template <bool INV, bool LINES_FAST, int NT, int EPT, typename T>
-__device__ void lds_fft(cx<T>* buf, const LdsLines& L, const AxisSched& S, const cx<T>* __restrict__ tw)
+template <bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In, class Out>
+__device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
+                                          const In& in, const Out& out, const cx<T>* __restrict__ tw)
 {
-    for (int s = 0; s < S.nst; ++s) {
-        const int R = S.radix[s];
-        const int Ns = S.ns[s];
-        const cx<T>* t = tw + S.twoff[s];
-        switch (R) {
-        case 16: lds_stage<16, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
-        case 8: lds_stage<8, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
-        case 4: lds_stage<4, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
-        case 3: lds_stage<3, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
-        case 2: lds_stage<2, INV, LINES_FAST, NT, EPT, T>(buf, L, S.n, Ns, t); break;
-        default: break;
-        }
+    StageArg a;
+    a.n = S.n;
+    a.nlines = nlines;
+    a.Ns = S.ns[s];
+    a.mg_lines = mg_lines;
+    a.mg_nb = S.mg_nb[s];
+    a.mg_ns = S.mg_ns[s];
+    const cx<T>* t = tw + S.twoff[s];
+    switch (S.radix[s]) {
+    case 16: stage<16, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    case 8: stage<8, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    case 4: stage<4, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    case 3: stage<3, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    default: stage<2, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     }
+}
+
+// All stages of one axis over `nlines` lines: the first stage reads through
+// `in`, the last writes through `out`, the stages between exchange through
+// the LDS tile `lds`.  in/out may themselves be the LDS tile.  Barriers are
+// placed from the accessor kinds: a stage that writes LDS ends with one; a
+// stage whose input and output may alias has one between reads and writes.
+// The caller guarantees the tile is ready (barrier) before the call.
+// n == 1 (no stages) is a plain copy from in to out.
+template <bool INV, bool LINES_FAST, int NT, int EPT, typename T, class In, class Out>
+__device__ __forceinline__ void fft_lines(const In& in, const LdsIO<T>& lds, const Out& out, int nlines,
+                                          const AxisSched& S, const cx<T>* __restrict__ tw)
+{
+    constexpr bool IL = In::kLds, OL = Out::kLds;
+    const int nst = S.nst;
+    const uint32_t mgl = lds.L.mg_lines;
+    if (nst == 0) {  // n == 1: a copy, unless in and out are the same tile
+        if (!(IL && OL)) {
+            for (int w = (int)threadIdx.x; w < nlines; w += NT) out.st(w, 0, in.ld(w, 0));
+            if (OL) __syncthreads();
+        }
+        return;
+    }
+    if (nst == 1) {
+        // single stage: in -> out; global in place needs the middle barrier too
+        stage_any<INV, LINES_FAST, NT, EPT, (IL == OL), OL, T>(S, 0, nlines, mgl, in, out, tw);
+        return;
+    }
+    stage_any<INV, LINES_FAST, NT, EPT, IL, true, T>(S, 0, nlines, mgl, in, lds, tw);
+    for (int s = 1; s < nst - 1; ++s)
+        stage_any<INV, LINES_FAST, NT, EPT, true, true, T>(S, s, nlines, mgl, lds, lds, tw);
+    stage_any<INV, LINES_FAST, NT, EPT, OL, OL, T>(S, nst - 1, nlines, mgl, lds, out, tw);
 }
 
 // ------------------------------------------------- real <-> half-length --
@@ -272,13 +493,13 @@ __device__ void lds_fft(cx<T>* buf, const LdsLines& L, const AxisSched& S, const
 //            Z[0] = (Re X0 + Re Xh) + i (Re X0 - Re Xh)
 //            (the imaginary parts of X[0] and X[h] are never read).
 template <int NT, typename T>
-__device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, int h,
+__device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, int h, uint32_t mg_pairs,
                                            const cx<T>* __restrict__ post)
 {
     const int npair = h / 2 + 1;  // k = 0 .. h/2
     const int total = rows * npair;
     for (int e = (int)threadIdx.x; e < total; e += NT) {
-        const int q = e / npair;
+        const int q = fdiv(e, mg_pairs);
         const int k = e - q * npair;
         cx<T>* Z = buf + q * rstride;
         if (k == 0) {
@@ -299,13 +520,13 @@ __device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, in
 }
 
 template <int NT, typename T>
-__device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int rstride, int h,
+__device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int rstride, int h, uint32_t mg_pairs,
                                            const cx<T>* __restrict__ post)
 {
     const int npair = h / 2 + 1;
     const int total = rows * npair;
     for (int e = (int)threadIdx.x; e < total; e += NT) {
-        const int q = e / npair;
+        const int q = fdiv(e, mg_pairs);
         const int k = e - q * npair;
         cx<T>* Z = buf + q * rstride;
         if (k == 0) {

@@ -1,0 +1,68 @@
+// fft3d_dispatch.cpp -- host-side selection of the per-dtype kernel entry
+// points, and the device set-up of the cooperative plane step.
+#include "fft3d_internal.hpp"
+
+namespace fft3d {
+
+hipError_t coop_setup(Plan& p)
+{
+    if (!p.coop) return hipSuccess;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = p.dtype ? coop_occupancy_f64(p, &per_cu) : coop_occupancy_f32(p, &per_cu);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    p.coop_grid = cus * per_cu;
+    const int tasks = p.coop_rt + p.coop_ct;
+    // slots per queue: every plane, the first empty slot, the lag, and one
+    // slot per workgroup that may still take tickets beyond them before it
+    // reaches a second-phase ticket of an empty plane and leaves
+    (void)tasks;
+    p.coop_nslots = (int)p.n0 + p.coop_lag + p.coop_grid + 2;
+    p.coop_ctr_count = 2 + kCoopQueues + (int64_t)kCoopQueues * 2 * p.coop_nslots;
+    e = hipMalloc(&p.d_ctr, (size_t)p.coop_ctr_count * sizeof(int));
+    if (e != hipSuccess) return e;
+    return hipMemset(p.d_ctr, 0, (size_t)p.coop_ctr_count * sizeof(int));
+}
+
+// Raising the dynamic-LDS limit is advisory: a launch that still exceeds what
+// the device allows fails with a launch error, which the callers report.
+hipError_t kernels_init()
+{
+    (void)init_plain_f32();
+    (void)init_plain_f64();
+    (void)init_coop_f32();
+    (void)init_coop_f64();
+    (void)hipGetLastError();
+    return hipSuccess;
+}
+
+hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inverse, hipStream_t st)
+{
+    return p.dtype ? launch_plane_coop_f64(p, in, out, inverse, st) : launch_plane_coop_f32(p, in, out, inverse, st);
+}
+hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st)
+{
+    return p.dtype ? launch_plane_r2c_f64(p, x, X, st) : launch_plane_r2c_f32(p, x, X, st);
+}
+hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t st)
+{
+    return p.dtype ? launch_plane_c2r_f64(p, X, y, st) : launch_plane_c2r_f32(p, X, y, st);
+}
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int rev, hipStream_t st)
+{
+    return p.dtype ? launch_rows_r2c_f64(p, x, X, rev, st) : launch_rows_r2c_f32(p, x, X, rev, st);
+}
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int rev, hipStream_t st)
+{
+    return p.dtype ? launch_rows_c2r_f64(p, X, y, rev, st) : launch_rows_c2r_f32(p, X, y, rev, st);
+}
+hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
+                       bool inverse, int rev, hipStream_t st)
+{
+    return p.dtype ? launch_cols_f64(p, cp, axis, tw_off, in, out, inverse, rev, st)
+                   : launch_cols_f32(p, cp, axis, tw_off, in, out, inverse, rev, st);
+}
+
+}  // namespace fft3d

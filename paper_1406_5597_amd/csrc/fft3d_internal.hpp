@@ -18,16 +18,19 @@ namespace fft3d {
 constexpr int kLdsMax = 160 * 1024;
 constexpr int kLdsHalf = 80 * 1024;
 
-// Thread counts / elements-per-thread of the two kernel tiers.
-constexpr int kNtSmall = 256;
+// Thread counts / elements-per-thread of the two kernel tiers.  A tile of
+// NT*EPT elements; every thread holds EPT elements in registers during a
+// stage.  Small tier: 64 KB tiles, two workgroups per CU; big tier: up to the
+// whole 160 KB of LDS.
+constexpr int kNtSmall = 512;
 constexpr int kNtBig = 512;
 template <typename T> struct Tier;
 template <> struct Tier<float> {
-    static constexpr int kEptSmall = 32;  // 8192 elements, 64 KB
+    static constexpr int kEptSmall = 16;  // 8192 elements, 64 KB
     static constexpr int kEptBig = 40;    // 20480 elements, 160 KB
 };
 template <> struct Tier<double> {
-    static constexpr int kEptSmall = 16;  // 4096 elements, 64 KB
+    static constexpr int kEptSmall = 8;   // 4096 elements, 64 KB
     static constexpr int kEptBig = 20;    // 10240 elements, 160 KB
 };
 
@@ -72,6 +75,18 @@ struct Plan {
     ColPass pass1;             // n1 columns of each plane (split)
     ColPass pass0;             // n0 columns over C (the strided step)
 
+    // cooperative plane step (split planes done in one launch, see k_plane_coop)
+    bool coop = false;
+    int coop_rt = 0, coop_ct = 0;  // row / column tasks per plane
+    int coop_rpw = 0, coop_w = 0;  // rows per row task, columns per column task
+    size_t coop_lds = 0;
+    int coop_grid = 0;             // set with the device state
+    int coop_nslots = 0;
+    int coop_lag = 2;              // slots between a plane's two phases
+    int64_t coop_ctr_count = 0;
+    int* d_ctr = nullptr;
+    AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h
+
     // device state
     bool has_device = false;
     int device = -1;
@@ -82,7 +97,7 @@ struct Plan {
 
 // Build the host part of a plan (schedules, tables, strategy).  Returns an
 // FFT3D_* code; `why` receives a message on failure.
-int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, std::string& why);
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why);
 
 // Factor n = 2^a 3^b into stages; false if n has another prime factor.
 bool make_schedule(int64_t n, AxisSched& s);
@@ -90,14 +105,40 @@ bool make_schedule(int64_t n, AxisSched& s);
 // e^{-2 pi i e/m}, quadrant-reduced, in long double.
 void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s);
 
+// Work queues of the cooperative plane step: one per XCD (8 on MI355X; the
+// queue index is the hardware XCC id masked to this many).
+constexpr int kCoopQueues = 16;
+
+// Per-dtype entry points (fft3d_kern_*.hip, fft3d_coop_*.hip).
+#define FFT3D_DECLARE_DTYPE(sfx)                                                                            \
+    hipError_t init_plain_##sfx();                                                                         \
+    hipError_t init_coop_##sfx();                                                                          \
+    hipError_t coop_occupancy_##sfx(const Plan& p, int* per_cu);                                           \
+    hipError_t launch_plane_coop_##sfx(const Plan& p, const void* in, void* out, bool inverse, hipStream_t s); \
+    hipError_t launch_plane_r2c_##sfx(const Plan& p, const void* x, void* X, hipStream_t s);               \
+    hipError_t launch_plane_c2r_##sfx(const Plan& p, const void* X, void* y, hipStream_t s);               \
+    hipError_t launch_rows_r2c_##sfx(const Plan& p, const void* x, void* X, int rev, hipStream_t s);       \
+    hipError_t launch_rows_c2r_##sfx(const Plan& p, const void* X, void* y, int rev, hipStream_t s);       \
+    hipError_t launch_cols_##sfx(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, \
+                                 void* out, bool inverse, int rev, hipStream_t s);
+FFT3D_DECLARE_DTYPE(f32)
+FFT3D_DECLARE_DTYPE(f64)
+#undef FFT3D_DECLARE_DTYPE
+
 // Launchers (enqueue on `stream`, no allocation, no synchronisation).
 hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
 hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
-hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
-hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
-hipError_t launch_cols(const Plan& p, const ColPass& cp, const AxisSched& ax, int64_t tw_off,
-                       const void* in, void* out, bool inverse, hipStream_t stream);
+// rev: walk each XCD's chunk of tiles from its end (see xcd_tile).
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int rev, hipStream_t stream);
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int rev, hipStream_t stream);
+// axis: 0 = n0, 1 = n1 (index into the plan's device schedules).
+hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
+                       bool inverse, int rev, hipStream_t stream);
+hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inverse, hipStream_t stream);
 // Raise the dynamic-LDS limit of every kernel once per process.
 hipError_t kernels_init();
+// Device part of the cooperative plane step: grid from occupancy on the
+// current device, counter block allocation.  No-op unless p.coop.
+hipError_t coop_setup(Plan& p);
 
 }  // namespace fft3d

@@ -1,0 +1,31 @@
+// fft3d_kern_f64.hip -- double instantiations of the standalone kernels
+// (plane, rows, strided columns); see fft3d_kernels.hpp.
+#include "fft3d_kernels.hpp"
+
+namespace fft3d {
+
+hipError_t init_plain_f64() { return init_plain<double>(); }
+hipError_t launch_plane_r2c_f64(const Plan& p, const void* x, void* X, hipStream_t s)
+{
+    return plane_r2c_t<double>(p, x, X, s);
+}
+hipError_t launch_plane_c2r_f64(const Plan& p, const void* X, void* y, hipStream_t s)
+{
+    return plane_c2r_t<double>(p, X, y, s);
+}
+hipError_t launch_rows_r2c_f64(const Plan& p, const void* x, void* X, int rev, hipStream_t s)
+{
+    return rows_r2c_t<double>(p, x, X, rev, s);
+}
+hipError_t launch_rows_c2r_f64(const Plan& p, const void* X, void* y, int rev, hipStream_t s)
+{
+    return rows_c2r_t<double>(p, X, y, rev, s);
+}
+hipError_t launch_cols_f64(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in,
+                           void* out, bool inverse, int rev, hipStream_t s)
+{
+    return inverse ? cols_t<double, true>(p, cp, axis, tw_off, in, out, rev, s)
+                   : cols_t<double, false>(p, cp, axis, tw_off, in, out, rev, s);
+}
+
+}  // namespace fft3d

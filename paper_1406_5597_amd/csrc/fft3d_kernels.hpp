@@ -1,0 +1,659 @@
+// fft3d_kernels.hip -- HIP kernels of the 3D r2c/c2r path for gfx950.
+//
+// The forward transform runs the paper's two steps (Sec. 2.1 items 1 and 3,
+// without the transpose of item 2, Sec. 2.2):
+//   step 1, plane r2c: every n1 x n2 real plane -> n1 x H complex (H = n2/2+1),
+//           n2 rows (half-length complex FFT + split) then n1 columns;
+//   step 3, strided column c2c: a length-n0 DFT down every flattened column
+//           c = k1*H + k2 of the natural-order spectrum, element stride n1*H,
+//           read and written in place -- the data stay in natural order.
+// The inverse runs the same steps in reverse order (Sec. 2.1, last sentence).
+//
+// All kernels stage one tile through LDS: a coalesced global->LDS copy, the
+// Stockham stages of fft3d_device.hpp on lines in LDS, a coalesced LDS->global
+// copy.  Plane tiles hold whole planes when they fit in LDS (fused plane
+// kernels); larger planes take a rows kernel and a strided n1 column pass.
+// Column tiles are W consecutive columns by all rows, so each row of a tile is
+// one contiguous W-element segment of memory.
+#pragma once
+
+#include "fft3d_device.hpp"
+#include "fft3d_internal.hpp"
+
+namespace fft3d {
+
+// ------------------------------------------------------------- kernels --
+
+// div_magic on the device, for a partial last group of planes (uniform, rare).
+__device__ __forceinline__ uint32_t div_magic_dev(uint32_t d)
+{
+    return d <= 1 ? 0u : (uint32_t)((1ull << 32) / d + 1);
+}
+
+// Contiguous copy of `count` elements by the workgroup, 8 loads in flight per
+// thread before the matching stores.  LP / SP: cache policies.
+template <typename T, int NT, int LP = LD_PLAIN, int SP = ST_PLAIN>
+__device__ __forceinline__ void copy_block(cx<T>* dst, const cx<T>* src, int count)
+{
+    constexpr int U = 8;
+    for (int base = 0; base < count; base += U * NT) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            v[u] = load_cx<LP, T>(src + (e < count ? e : count - 1));  // always a valid address
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            if (e < count) store_cx<SP, T>(dst + e, v[u]);
+        }
+    }
+}
+
+// LDS view of `rows` rows of H slots (lines along a row).
+// (Lines along a row never need the line-count magic: the row mapping
+// divides by the butterflies per line instead.)
+template <typename T> __device__ __forceinline__ LdsIO<T> lds_rows(cx<T>* buf, int rows, int H)
+{
+    LdsIO<T> l;
+    l.buf = buf;
+    l.L.nlines = rows;
+    l.L.lpp = rows;
+    l.L.sp = 0;
+    l.L.sw = H;
+    l.L.si = 1;
+    l.L.mg_lines = 0;
+    l.L.mg_lpp = 0;
+    return l;
+}
+
+// LDS view of the columns of np planes of n1 x H (lines down a column).
+template <typename T>
+__device__ __forceinline__ LdsIO<T> lds_plane_cols(cx<T>* buf, int np, int n1, int H, uint32_t mg_lines,
+                                                   uint32_t mgH)
+{
+    LdsIO<T> l;
+    l.buf = buf;
+    l.L.nlines = np * H;
+    l.L.lpp = H;
+    l.L.sp = n1 * H;
+    l.L.sw = 1;
+    l.L.si = H;
+    l.L.mg_lines = mg_lines;
+    l.L.mg_lpp = mgH;
+    return l;
+}
+
+// ---- tiles: the unit of work of every kernel ----
+
+// Length-n transforms down `width` (<= W) consecutive columns of a row-major
+// block, row stride S; src and dst may be equal.  LP / SP: cache policies.
+template <typename T, int NT, int EPT, bool INV, int LP = LD_PLAIN, int SP = ST_PLAIN>
+__device__ __forceinline__ void col_tile(const cx<T>* src, cx<T>* dst, int64_t S, int width, int W,
+                                         uint32_t mg_w, const AxisSched& ax, const cx<T>* __restrict__ tw,
+                                         cx<T>* buf)
+{
+    ColTileIO<T, LP, SP> g;
+    g.src = src;
+    g.dst = dst;
+    g.S = S;
+    g.width = width;
+    LdsIO<T> l;
+    l.buf = buf;
+    l.L.nlines = W;
+    l.L.lpp = W;
+    l.L.sp = 0;
+    l.L.sw = 1;
+    l.L.si = W;
+    l.L.mg_lines = mg_w;
+    l.L.mg_lpp = mg_w;
+    fft_lines<INV, true, NT, EPT, T>(g, l, g, W, ax, tw);
+}
+
+// `rows` real rows of length n2 (read as h = n2/2 complex values
+// z[m] = x[2m] + i x[2m+1]) -> `rows` rows of H = h+1 bins, contiguous.
+// LP: cache policy of the input loads, SP: of the output stores.
+template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
+__device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int rows, const AxisSched& axh,
+                                              const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
+                                              cx<T>* buf)
+{
+    const int h = axh.n, H = h + 1;
+    RowsIO<T, LP> g;
+    g.src = xz;
+    g.dst = nullptr;
+    g.len = h;
+    const LdsIO<T> l = lds_rows<T>(buf, rows, H);
+    fft_lines<false, false, NT, EPT, T>(g, l, l, rows, axh, tw);
+    split_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    copy_block<T, NT, LD_PLAIN, SP>(Xo, buf, rows * H);
+}
+
+// `rows` rows of H bins -> `rows` real rows of length n2.  LP: cache policy
+// of the bin loads, SP: of the output stores.
+template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
+__device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int rows, const AxisSched& axh,
+                                              const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
+                                              cx<T>* buf)
+{
+    const int h = axh.n, H = h + 1;
+    copy_block<T, NT, LP>(buf, Xi, rows * H);
+    __syncthreads();
+    merge_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    RowsIO<T, LD_PLAIN, SP> g;
+    g.src = nullptr;
+    g.dst = yz;
+    g.len = h;
+    const LdsIO<T> l = lds_rows<T>(buf, rows, H);
+    fft_lines<true, false, NT, EPT, T>(l, l, g, rows, axh, tw);
+}
+
+// ---- standalone kernels ----
+
+template <typename T, int NT, int EPT, bool INV>
+__global__ __launch_bounds__(NT) void k_cols(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
+                                             const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
+                                             int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
+                                             int reverse)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x, reverse);
+    const int64_t b = t / tiles_per_batch;
+    const int64_t c0 = (t - b * tiles_per_batch) * W;
+    const int64_t rem = ncols - c0;
+    const int width = rem < (int64_t)W ? (int)rem : W;
+    col_tile<T, NT, EPT, INV>(in + b * bstride + c0, out + b * bstride + c0, S, width, W, mg_w, *axp, tw, buf);
+}
+
+// Split-plane forward: rpw real rows of length n2 -> rpw rows of H bins.
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
+                                                 const cx<T>* __restrict__ tw,
+                                                 const cx<T>* __restrict__ post, int64_t nrows,
+                                                 int rpw, int reverse)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& axh = *axp;
+    const int h = axh.n, H = h + 1;
+    const int64_t row0 = xcd_tile(blockIdx.x, gridDim.x, reverse) * rpw;
+    const int64_t left = nrows - row0;
+    const int rows = left < rpw ? (int)left : rpw;
+    rows_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + row0 * h, X + row0 * H, rows, axh, tw, post,
+                              buf);
+}
+
+// Split-plane inverse: rpw rows of H bins -> rpw real rows of length n2.
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
+                                                 const cx<T>* __restrict__ tw,
+                                                 const cx<T>* __restrict__ post, int64_t nrows,
+                                                 int rpw, int reverse)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& axh = *axp;
+    const int h = axh.n, H = h + 1;
+    const int64_t row0 = xcd_tile(blockIdx.x, gridDim.x, reverse) * rpw;
+    const int64_t left = nrows - row0;
+    const int rows = left < rpw ? (int)left : rpw;
+    rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, axh, tw, post, buf);
+}
+
+// Fused plane forward: ppw whole planes per workgroup, held in LDS as
+// [plane][n1][H]: rows (from HBM), split, then the n1 columns (to HBM).
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axhp,
+                                                  const AxisSched* __restrict__ ax1p,
+                                                  const cx<T>* __restrict__ tw2,
+                                                  const cx<T>* __restrict__ post,
+                                                  const cx<T>* __restrict__ tw1, int64_t nplanes,
+                                                  int ppw, uint32_t mg_lines, uint32_t mgH)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& axh = *axhp;
+    const AxisSched& ax1 = *ax1p;
+    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int64_t p0 = (int64_t)blockIdx.x * ppw;
+    const int64_t left = nplanes - p0;
+    const int np = left < ppw ? (int)left : ppw;
+    const int rows = np * n1;
+    RowsIO<T> gi;
+    gi.src = reinterpret_cast<const cx<T>*>(x) + p0 * n1 * h;
+    gi.dst = nullptr;
+    gi.len = h;
+    const LdsIO<T> lr = lds_rows<T>(buf, rows, H);
+    fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, axh, tw2);
+    split_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    PlaneColsIO<T> go;
+    go.src = nullptr;
+    go.dst = X + p0 * n1 * H;
+    go.H = H;
+    go.plane = n1 * H;
+    go.mgH = mgH;
+    const LdsIO<T> lc = lds_plane_cols<T>(buf, np, n1, H, np == ppw ? mg_lines : div_magic_dev(np * H), mgH);
+    fft_lines<false, true, NT, EPT, T>(lc, lc, go, np * H, ax1, tw1);
+}
+
+// Fused plane inverse: n1 columns (from HBM), merge, rows (to HBM).
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axhp,
+                                                  const AxisSched* __restrict__ ax1p,
+                                                  const cx<T>* __restrict__ tw2,
+                                                  const cx<T>* __restrict__ post,
+                                                  const cx<T>* __restrict__ tw1, int64_t nplanes,
+                                                  int ppw, uint32_t mg_lines, uint32_t mgH)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& axh = *axhp;
+    const AxisSched& ax1 = *ax1p;
+    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int64_t p0 = (int64_t)blockIdx.x * ppw;
+    const int64_t left = nplanes - p0;
+    const int np = left < ppw ? (int)left : ppw;
+    const int rows = np * n1;
+    PlaneColsIO<T> gi;
+    gi.src = X + p0 * n1 * H;
+    gi.dst = nullptr;
+    gi.H = H;
+    gi.plane = n1 * H;
+    gi.mgH = mgH;
+    const LdsIO<T> lc = lds_plane_cols<T>(buf, np, n1, H, np == ppw ? mg_lines : div_magic_dev(np * H), mgH);
+    fft_lines<true, true, NT, EPT, T>(gi, lc, lc, np * H, ax1, tw1);
+    merge_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    RowsIO<T> go;
+    go.src = nullptr;
+    go.dst = reinterpret_cast<cx<T>*>(y) + p0 * n1 * h;
+    go.len = h;
+    const LdsIO<T> lr = lds_rows<T>(buf, rows, H);
+    fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, axh, tw2);
+}
+
+// ---- cooperative plane step for planes larger than LDS ----
+//
+// One persistent launch does the whole plane step.  Each workgroup reads the
+// XCD it runs on (hardware register XCC_ID) and takes tickets from that
+// XCD's queue.  Tickets come in slots of T = RT + CT tasks.  Slot s first
+// holds the first-phase tasks of plane P(s) (forward: RT row tasks, rpw rows
+// each: half-length FFT + split, written to X; inverse: CT column tasks, W
+// columns of the plane down n1, in place), then the second-phase tasks of
+// plane P(s - L) (forward: CT column tasks in place on X; inverse: RT row
+// tasks, merge + inverse rows to y).  A second-phase task waits until every
+// first-phase task of its plane has counted itself done; the lag of L slots
+// gives those tasks time to finish, so workgroups rarely wait.  P(s) is
+// claimed by the first ticket of slot s from a global plane counter, in slot
+// order within a queue (the claimer waits for slot s-1's claim), so once a
+// slot finds no plane left every later slot of the queue is empty too.
+// A plane's tasks all run on one XCD, so its intermediate stays in that
+// XCD's L2: producers drain their stores to L2 (s_waitcnt) before the count
+// goes up, consumers read with device-scope loads that miss L1.  Every wait
+// is for a smaller ticket than the waiter's own, held by a workgroup that is
+// running, so the kernel cannot deadlock whatever the placement of
+// workgroups; every wait is also bounded (spin limit), after which the
+// workgroup records an error and leaves.
+
+struct CoopArgs {
+    int64_t n0;
+    int n1, h, H;
+    int rpw, RT;         // rows per row task, row tasks per plane
+    int W, CT;           // column tile width, column tasks per plane
+    uint32_t mg_w;
+    int lag;             // L: slots between a plane's two phases
+    int nslots;          // slots per queue
+    int spin_limit;
+    const AxisSched* axh;
+    const AxisSched* ax1;
+    int64_t off_tw2, off_post, off_tw1;
+    int* ctr;  // [claim][error][ticket x kCoopQueues][queue][slot][plane+1 or -1, done]
+};
+
+__device__ __forceinline__ int coop_wait_nonzero(int* p, int limit)
+{
+    for (int it = 0; it < limit; ++it) {
+        const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v != 0) return v;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return 0;
+}
+
+__device__ __forceinline__ bool coop_wait_geq(int* p, int target, int limit)
+{
+    for (int it = 0; it < limit; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+enum { kCoopExit = 0, kCoopSkip = 1, kCoopTask = 2 };
+
+template <typename T, int NT, int EPT, bool INV>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_plane_coop(const void* in, void* out, const cx<T>* tw, CoopArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    __shared__ int s_task[4];
+    const int q = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kCoopQueues - 1);
+    int* ticket = a.ctr + 2 + q;
+    int* slots = a.ctr + 2 + kCoopQueues + (int64_t)q * 2 * a.nslots;
+    const int first = INV ? a.CT : a.RT;  // first-phase tasks per plane
+    const int TT = a.RT + a.CT;
+    const cx<T>* tw2 = tw + a.off_tw2;
+    const cx<T>* post = tw + a.off_post;
+    const cx<T>* tw1 = tw + a.off_tw1;
+    const int h = a.h, H = a.H, n1 = a.n1;
+    for (;;) {
+        __syncthreads();  // the previous task is done with LDS and s_task
+        if (threadIdx.x == 0) {
+            int kind = kCoopExit, pl = 0, k = 0, ps = 0;
+            const int t = atomicAdd(ticket, 1);
+            const int s = t / TT;
+            k = t - s * TT;
+            if (s >= a.nslots) {
+                atomicOr(&a.ctr[1], 4);
+            } else if (k < first) {
+                // first phase of plane P(s)
+                int* slot = slots + 2 * s;
+                int v;
+                if (k == 0) {
+                    const int prev = s > 0 ? coop_wait_nonzero(slot - 2, a.spin_limit) : 1;
+                    if (prev == 0) {
+                        atomicOr(&a.ctr[1], 1);
+                        v = 0;
+                    } else if (prev < 0) {
+                        v = -1;
+                    } else {
+                        const int c = atomicAdd(&a.ctr[0], 1);
+                        v = c < a.n0 ? c + 1 : -1;
+                    }
+                    if (v != 0) __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    v = coop_wait_nonzero(slot, a.spin_limit);
+                    if (v == 0) atomicOr(&a.ctr[1], 1);
+                }
+                if (v > 0) {
+                    kind = kCoopTask;
+                    pl = v - 1;
+                    ps = s;
+                } else if (v < 0) {
+                    kind = kCoopSkip;  // later second-phase tickets may still have work
+                }
+            } else if (s < a.lag) {
+                kind = kCoopSkip;
+            } else {
+                // second phase of plane P(s - L)
+                int* slot = slots + 2 * (s - a.lag);
+                const int v = coop_wait_nonzero(slot, a.spin_limit);
+                if (v > 0) {
+                    if (coop_wait_geq(slot + 1, first, a.spin_limit)) {
+                        kind = kCoopTask;
+                        pl = v - 1;
+                        ps = s - a.lag;
+                    } else {
+                        atomicOr(&a.ctr[1], 2);
+                    }
+                } else if (v == 0) {
+                    atomicOr(&a.ctr[1], 1);
+                }
+                // v < 0: no plane there, nor in any later slot: leave
+            }
+            s_task[0] = kind;
+            s_task[1] = pl;
+            s_task[2] = k;
+            s_task[3] = ps;
+        }
+        __syncthreads();
+        const int kind = s_task[0], pl = s_task[1], k = s_task[2], ps = s_task[3];
+        if (kind == kCoopExit) break;
+        if (kind == kCoopSkip) continue;
+        const int64_t plane = (int64_t)pl * n1 * H;  // complex offset of the plane
+        const bool first_phase = k < first;
+        const int ktask = first_phase ? k : k - first;
+        const bool row_task = INV ? !first_phase : first_phase;
+        if (row_task) {
+            const int r0 = ktask * a.rpw;
+            const int rows = n1 - r0 < a.rpw ? n1 - r0 : a.rpw;
+            if (!INV) {
+                const cx<T>* xz = reinterpret_cast<const cx<T>*>(in) + ((int64_t)pl * n1 + r0) * h;
+                cx<T>* Xo = reinterpret_cast<cx<T>*>(out) + plane + (int64_t)r0 * H;
+                // input read once (streamed); the intermediate stays in L2
+                rows_r2c_tile<T, NT, EPT, LD_STREAM, ST_PLAIN>(xz, Xo, rows, *a.axh, tw2, post, buf);
+            } else {
+                const cx<T>* Xi = reinterpret_cast<const cx<T>*>(in) + plane + (int64_t)r0 * H;
+                cx<T>* yz = reinterpret_cast<cx<T>*>(out) + ((int64_t)pl * n1 + r0) * h;
+                // the intermediate comes from L2; the output is streamed
+                rows_c2r_tile<T, NT, EPT, LD_L2, ST_STREAM>(Xi, yz, rows, *a.axh, tw2, post, buf);
+            }
+        } else {
+            const int c0 = ktask * a.W;
+            const int width = H - c0 < a.W ? H - c0 : a.W;
+            if (!INV) {
+                cx<T>* X = reinterpret_cast<cx<T>*>(out) + plane + c0;
+                col_tile<T, NT, EPT, false, LD_L2, ST_STREAM>(X, X, H, width, a.W, a.mg_w, *a.ax1, tw1, buf);
+            } else {
+                cx<T>* B = const_cast<cx<T>*>(reinterpret_cast<const cx<T>*>(in)) + plane + c0;
+                col_tile<T, NT, EPT, true, LD_STREAM, ST_PLAIN>(B, B, H, width, a.W, a.mg_w, *a.ax1, tw1, buf);
+            }
+        }
+        if (first_phase) {
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+            __syncthreads();                // ... and every wave's
+            if (threadIdx.x == 0) atomicAdd(&slots[2 * ps + 1], 1);
+        }
+    }
+}
+
+template <int Unused = 0> __global__ void k_zero_ints(int* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ----------------------------------------------------------- launchers --
+// Templates instantiated per dtype in fft3d_kern_{f32,f64}.hip (plain kernels)
+// and fft3d_coop_{f32,f64}.hip (cooperative plane kernel).
+
+
+
+template <typename T> const cx<T>* table(const Plan& p, int64_t off)
+{
+    return reinterpret_cast<const cx<T>*>(p.d_tw) + off;
+}
+
+// Device copies of the schedules: [n0, n1, n2/2].
+inline const AxisSched* dsched(const Plan& p, int axis) { return p.d_sched + axis; }
+
+template <typename K> hipError_t allow_lds(K kernel)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+}
+
+template <typename T> hipError_t init_plain()
+{
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    hipError_t e = hipSuccess;
+#define FFT3D_ALLOW(k)                       \
+    do {                                     \
+        hipError_t r_ = allow_lds(k);        \
+        if (r_ != hipSuccess) e = r_;        \
+    } while (0)
+    FFT3D_ALLOW((k_cols<T, kNtSmall, ES, false>));
+    FFT3D_ALLOW((k_cols<T, kNtSmall, ES, true>));
+    FFT3D_ALLOW((k_cols<T, kNtBig, EB, false>));
+    FFT3D_ALLOW((k_cols<T, kNtBig, EB, true>));
+    FFT3D_ALLOW((k_rows_r2c<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_rows_r2c<T, kNtBig, EB>));
+    FFT3D_ALLOW((k_rows_c2r<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_rows_c2r<T, kNtBig, EB>));
+    FFT3D_ALLOW((k_plane_r2c<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_plane_r2c<T, kNtBig, EB>));
+    FFT3D_ALLOW((k_plane_c2r<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_plane_c2r<T, kNtBig, EB>));
+#undef FFT3D_ALLOW
+    return e;
+}
+
+template <typename T> hipError_t init_coop()
+{
+    constexpr int ES = Tier<T>::kEptSmall;
+    hipError_t a = allow_lds(k_plane_coop<T, kNtSmall, ES, false>);
+    hipError_t b = allow_lds(k_plane_coop<T, kNtSmall, ES, true>);
+    return a != hipSuccess ? a : b;
+}
+
+template <typename T>
+hipError_t plane_r2c_t(const Plan& p, const void* x, void* X, hipStream_t st)
+{
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const unsigned grid = (unsigned)((p.n0 + p.ppw - 1) / p.ppw);
+    const T* xi = static_cast<const T*>(x);
+    cx<T>* Xo = static_cast<cx<T>*>(X);
+    if (p.plane_big)
+        hipLaunchKernelGGL((k_plane_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, xi,
+                           Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
+                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+    else
+        hipLaunchKernelGGL((k_plane_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
+                           xi, Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
+                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st)
+{
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const unsigned grid = (unsigned)((p.n0 + p.ppw - 1) / p.ppw);
+    const cx<T>* Xi = static_cast<const cx<T>*>(X);
+    T* yo = static_cast<T*>(y);
+    if (p.plane_big)
+        hipLaunchKernelGGL((k_plane_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, Xi,
+                           yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
+                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+    else
+        hipLaunchKernelGGL((k_plane_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
+                           Xi, yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
+                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int rev, hipStream_t st)
+{
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const int64_t nrows = p.n0 * p.n1;
+    const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
+    const T* xi = static_cast<const T*>(x);
+    cx<T>* Xo = static_cast<cx<T>*>(X);
+    if (p.rows_big)
+        hipLaunchKernelGGL((k_rows_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+    else
+        hipLaunchKernelGGL((k_rows_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, xi,
+                           Xo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int rev, hipStream_t st)
+{
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const int64_t nrows = p.n0 * p.n1;
+    const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
+    const cx<T>* Xi = static_cast<const cx<T>*>(X);
+    T* yo = static_cast<T*>(y);
+    if (p.rows_big)
+        hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+    else
+        hipLaunchKernelGGL((k_rows_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
+                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+    return hipGetLastError();
+}
+
+template <typename T, bool INV>
+hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
+                  int rev, hipStream_t st)
+{
+    const AxisSched* ax = dsched(p, axis);
+    constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const unsigned grid = (unsigned)(cp.nbatch * cp.tiles_per_batch);
+    const cx<T>* ci = static_cast<const cx<T>*>(in);
+    cx<T>* co = static_cast<cx<T>*>(out);
+    if (cp.big)
+        hipLaunchKernelGGL((k_cols<T, kNtBig, EB, INV>), dim3(grid), dim3(kNtBig), cp.lds, st, ci, co, ax,
+                           table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, rev);
+    else
+        hipLaunchKernelGGL((k_cols<T, kNtSmall, ES, INV>), dim3(grid), dim3(kNtSmall), cp.lds, st, ci, co,
+                           ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, rev);
+    return hipGetLastError();
+}
+
+template <typename T> CoopArgs coop_args(const Plan& p)
+{
+    CoopArgs a;
+    a.n0 = p.n0;
+    a.n1 = (int)p.n1;
+    a.h = (int)p.h;
+    a.H = (int)p.H;
+    a.rpw = p.coop_rpw;
+    a.RT = p.coop_rt;
+    a.W = p.coop_w;
+    a.CT = p.coop_ct;
+    a.mg_w = div_magic((uint32_t)p.coop_w);
+    a.nslots = p.coop_nslots;
+    a.spin_limit = 1 << 22;
+    a.axh = dsched(p, 2);
+    a.ax1 = dsched(p, 1);
+    a.lag = p.coop_lag;
+    a.off_tw2 = p.off_ax2h;
+    a.off_post = p.off_post;
+    a.off_tw1 = p.off_ax1;
+    a.ctr = p.d_ctr;
+    return a;
+}
+
+template <typename T>
+hipError_t coop_t(const Plan& p, const void* in, void* out, bool inverse, hipStream_t st)
+{
+    constexpr int ES = Tier<T>::kEptSmall;
+    hipLaunchKernelGGL(k_zero_ints<0>, dim3(64), dim3(256), 0, st, p.d_ctr, p.coop_ctr_count);
+    const CoopArgs a = coop_args<T>(p);
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(p.d_tw);
+    if (inverse)
+        hipLaunchKernelGGL((k_plane_coop<T, kNtSmall, ES, true>), dim3(p.coop_grid), dim3(kNtSmall), p.coop_lds,
+                           st, in, out, tw, a);
+    else
+        hipLaunchKernelGGL((k_plane_coop<T, kNtSmall, ES, false>), dim3(p.coop_grid), dim3(kNtSmall), p.coop_lds,
+                           st, in, out, tw, a);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t coop_occupancy(const Plan& p, int* per_cu)
+{
+    constexpr int ES = Tier<T>::kEptSmall;
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &a, reinterpret_cast<const void*>(k_plane_coop<T, kNtSmall, ES, false>), kNtSmall, p.coop_lds);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, reinterpret_cast<const void*>(k_plane_coop<T, kNtSmall, ES, true>), kNtSmall, p.coop_lds);
+    if (e != hipSuccess) return e;
+    *per_cu = a < b ? a : b;
+    return hipSuccess;
+}
+
+
+}  // namespace fft3d

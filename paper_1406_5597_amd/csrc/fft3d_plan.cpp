@@ -2,6 +2,7 @@
 // the choice of kernels and tile shapes.  Runs once per (shape, dtype).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <string>
@@ -51,10 +52,14 @@ bool make_schedule(int64_t n, AxisSched& s)
         s.radix[i] = radices[i];
         s.ns[i] = ns;
         s.twoff[i] = off;
+        s.mg_ns[i] = div_magic((uint32_t)ns);
+        s.mg_nb[i] = div_magic((uint32_t)(n / radices[i]));
         if (ns > 1) off += ns * (radices[i] - 1);
         ns *= radices[i];
     }
     s.nst = cnt;
+    s.mg_n = div_magic((uint32_t)n);
+    s.mg_pairs = div_magic((uint32_t)(n / 2 + 1));
     return true;
 }
 
@@ -166,7 +171,7 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     return true;
 }
 
-int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, std::string& why)
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why)
 {
     char msg[256];
     if (n0 < 1 || n1 < 1 || n2 < 1) {
@@ -255,10 +260,44 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, std:
             why = "n1 too large for a column tile";
             return FFT3D_ERR_UNSUPPORTED;
         }
+        // one cooperative launch for the plane step when both task kinds fit
+        // the small tier (and the caller did not ask for the two-kernel path)
+        if (!(flags & FFT3D_PLAN_SPLIT_PLANE) && !p.rows_big && !p.pass1.big && n1 > 1) {
+            p.coop = true;
+            p.coop_rpw = p.rpw;
+            p.coop_w = p.pass1.W;
+            // tuning overrides (rows per row task, columns per column task, lag)
+            if (const char* v = getenv("FFT3D_COOP_RPW")) {
+                const int r = atoi(v);
+                if (r >= 1 && r <= p.rpw) p.coop_rpw = r;
+            }
+            if (const char* v = getenv("FFT3D_COOP_W")) {
+                const int w = atoi(v);
+                if (w >= 1 && w <= p.pass1.W && (w & (w - 1)) == 0) p.coop_w = w;
+            }
+            if (const char* lag = getenv("FFT3D_COOP_LAG")) p.coop_lag = std::max(0, atoi(lag));
+            p.coop_rt = (int)((n1 + p.coop_rpw - 1) / p.coop_rpw);
+            p.coop_ct = (int)((p.H + p.coop_w - 1) / p.coop_w);
+            p.coop_lds = (size_t)std::max<int64_t>(p.coop_rpw * p.H * cxs, n1 * p.coop_w * cxs);
+        }
     }
     if (!make_colpass(p.pass0, n0, p.C, p.C, 1, 0, cxs, es, eb)) {
         why = "n0 too large for a column tile";
         return FFT3D_ERR_UNSUPPORTED;
+    }
+    // tuning override of the n0 tile width (power of two; ignored if it does
+    // not fit a tier)
+    if (const char* w = getenv("FFT3D_N0_W")) {
+        ColPass cp = p.pass0;
+        const int W = atoi(w);
+        if (W >= 1 && (W & (W - 1)) == 0 && n0 * W <= eb && n0 * W * cxs <= kLdsMax) {
+            cp.W = W;
+            cp.wshift = ilog2(W);
+            cp.big = n0 * W > es || n0 * W * cxs > kLdsHalf;
+            cp.tiles_per_batch = (p.C + W - 1) / W;
+            cp.lds = (size_t)(n0 * W * cxs);
+            p.pass0 = cp;
+        }
     }
     return FFT3D_OK;
 }
@@ -302,21 +341,30 @@ std::string Plan::describe() const
         r += b;
     } else {
         snprintf(b, sizeof b,
-                 "\"plane\": {\"kind\": \"split\", \"rows_per_wg\": %d, \"tier\": \"%s\", \"grid\": %lld, "
-                 "\"lds\": %zu, \"n1_pass\": ",
-                 rpw, rows_big ? "big" : "small", (long long)((n0 * n1 + rpw - 1) / rpw), rows_lds);
+                 "\"plane\": {\"kind\": \"%s\", \"rows_per_wg\": %d, \"tier\": \"%s\", \"grid\": %lld, "
+                 "\"lds\": %zu, ",
+                 coop ? "coop" : "split", rpw, rows_big ? "big" : "small",
+                 (long long)((n0 * n1 + rpw - 1) / rpw), rows_lds);
         r += b;
-        r += pass_json(pass1) + "}, ";
+        if (coop) {
+            snprintf(b, sizeof b,
+                     "\"coop\": {\"row_tasks\": %d, \"col_tasks\": %d, \"grid\": %d, \"lds\": %zu, "
+                     "\"slots\": %d}, ",
+                     coop_rt, coop_ct, coop_grid, coop_lds, coop_nslots);
+            r += b;
+        }
+        r += "\"n1_pass\": " + pass_json(pass1) + "}, ";
     }
     r += "\"n0_pass\": " + pass_json(pass0) + ", ";
     // pass lists (FFT3D_PASS_* ids) of the two directions
     std::string f = "[0", i = "[";
-    if (!fused_plane && n1 > 1) f += ", 1";
+    const bool n1_pass = !fused_plane && !coop && n1 > 1;
+    if (n1_pass) f += ", 1";
     if (n0 > 1) {
         f += ", 2";
         i += "3, ";
     }
-    if (!fused_plane && n1 > 1) i += "4, ";
+    if (n1_pass) i += "4, ";
     r += "\"r2c_passes\": " + f + "], \"c2r_passes\": " + i + "5]}";
     return r;
 }

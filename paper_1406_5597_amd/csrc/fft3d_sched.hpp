@@ -8,13 +8,23 @@ namespace fft3d {
 
 constexpr int kMaxStages = 12;
 
+// Division by an invariant d in [1, 2^16) of an index n with n*d < 2^32:
+// n / d = mulhi32(n, magic(d)) with magic(d) = floor(2^32/d) + 1, and
+// magic(1) = 0 meaning "n / 1 = n".  Exactness: n*magic/2^32 exceeds n/d by
+// at most n/2^32 < 1/d, which cannot carry past the next integer.
+inline uint32_t div_magic(uint32_t d) { return d <= 1 ? 0u : (uint32_t)((1ull << 32) / d + 1); }
+
 // Radix schedule of one line length, as the kernels see it.
 struct AxisSched {
-    int32_t n;                  // line length
-    int32_t nst;                // number of stages (0 for n == 1)
-    int32_t radix[kMaxStages];  // radix of each stage
-    int32_t ns[kMaxStages];     // product of the radices before the stage
-    int32_t twoff[kMaxStages];  // offset of the stage's twiddles in the axis table
+    int32_t n;                   // line length
+    int32_t nst;                 // number of stages (0 for n == 1)
+    int32_t radix[kMaxStages];   // radix of each stage
+    int32_t ns[kMaxStages];      // product of the radices before the stage
+    int32_t twoff[kMaxStages];   // offset of the stage's twiddles in the axis table
+    uint32_t mg_ns[kMaxStages];  // div_magic(ns)
+    uint32_t mg_nb[kMaxStages];  // div_magic(n / radix): butterflies per line
+    uint32_t mg_n;               // div_magic(n)
+    uint32_t mg_pairs;           // div_magic(n/2 + 1): (k, n-k) pairs of a real split
 };
 
 // Lines in LDS: element i of line w lives at
@@ -23,10 +33,12 @@ struct AxisSched {
 // otherwise consecutive positions along a line (use when si == 1).
 struct LdsLines {
     int32_t nlines;
-    int32_t lpp;  // lines per panel
-    int32_t sp;   // panel stride
-    int32_t sw;   // line stride within a panel
-    int32_t si;   // element stride along a line
+    int32_t lpp;        // lines per panel
+    int32_t sp;         // panel stride
+    int32_t sw;         // line stride within a panel
+    int32_t si;         // element stride along a line
+    uint32_t mg_lines;  // div_magic(nlines)
+    uint32_t mg_lpp;    // div_magic(lpp)
 };
 
 }  // namespace fft3d

@@ -63,6 +63,37 @@ def test_r2c_c2r_match_oracle(F, oracle, shape, dtype):
     assert rel_l2(host(y3), x * np.prod(shape)) <= TOL[dtype]
 
 
+# planes larger than LDS: the cooperative one-launch plane step (default) and
+# the two-kernel split path share their tile code, so they agree bit for bit
+BIG_PLANES = [(24, 256, 256), (8, 512, 512), (6, 384, 768), (2, 2048, 16), (4, 16, 4096), (6, 512, 96),
+              (16, 288, 576), (4, 96, 1536)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", BIG_PLANES, ids=lambda s: "x".join(map(str, s)))
+def test_cooperative_plane_step_matches_split_and_oracle(F, oracle, shape, dtype):
+    say("coop vs split %s %s" % (shape, dtype))
+    x = rounded(fields.uniform(shape, seed=202), dtype)
+    pc = F.Plan(*shape, dtype=dtype)
+    ps = F.Plan(*shape, dtype=dtype, split_plane=True)
+    if pc.describe()["plane"]["kind"] != "coop":
+        pytest.skip("plane fits LDS in %s" % dtype)
+    assert ps.describe()["plane"]["kind"] == "split"
+    xd = dev_real(x, dtype)
+    Xc = F.r2c(pc, xd)
+    Xs = F.r2c(ps, xd)
+    assert bool((Xc == Xs).all())
+    assert rel_l2(host(Xc), oracle.r2c(x)) <= TOL[dtype]
+    for work in (True, False):
+        yc = F.c2r(pc, Xc.clone(), work=F.empty_complex(pc) if work else None)
+        ys = F.c2r(ps, Xs.clone(), work=F.empty_complex(ps) if work else None)
+        assert bool((yc == ys).all())
+        assert rel_l2(host(yc), x * np.prod(shape)) <= TOL[dtype]
+    # repeated calls on one plan reuse its counter block
+    for _ in range(3):
+        assert bool((F.r2c(pc, xd) == Xc).all())
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_c2r_non_hermitian_follows_definition(F, oracle, dtype):
     # arbitrary complex half spectrum: Im of the self-conjugate bins of each
