@@ -64,8 +64,8 @@ def pair_bytes_min(shape, elem: int) -> int:
     return 2 * (elem * N + 2 * elem * M)
 
 
-def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, split_plane=False):
-    plan = F.Plan(*shape, dtype=dtype, split_plane=split_plane)
+def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=False):
+    plan = F.Plan(*shape, dtype=dtype, coop_plane=coop_plane)
     desc = plan.describe()
     elem = 4 if dtype == "f32" else 8
     x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
@@ -173,8 +173,8 @@ def main() -> int:
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--split-plane", action="store_true",
-                    help="two-kernel plane step for large planes instead of the cooperative one")
+    ap.add_argument("--coop-plane", action="store_true",
+                    help="cooperative one-launch plane step for large planes instead of the two kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU form (the slab exchange "
@@ -197,7 +197,7 @@ def main() -> int:
     for d in dtypes:
         print("# timing %s ..." % d, file=sys.stderr, flush=True)
         results[d], keep[d] = run_dtype(F, torch, x64, shape, d, args.steps, args.warmup, fields,
-                                        args.split_plane)
+                                        args.coop_plane)
         print("# %s: %.3f ms/pair, %.1f pairs/s, dominant %s %.1f GB/s" % (
             d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
             results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)

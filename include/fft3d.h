@@ -81,9 +81,10 @@ enum { FFT3D_R2C = 0, FFT3D_C2R = 1, FFT3D_ROUNDTRIP = 2 };
 /* Plan flags for fft3d_plan_ex. */
 enum {
     FFT3D_PLAN_HOST_ONLY = 1,  /* build schedules/tables on the host only; cannot execute */
-    FFT3D_PLAN_SPLIT_PLANE = 2 /* planes larger than LDS: rows kernel + n1 column kernel
-                                  (two sweeps of HBM) instead of the default cooperative
-                                  one-launch plane step */
+    FFT3D_PLAN_COOP_PLANE = 2  /* planes larger than LDS: one cooperative persistent launch
+                                  for the plane step (rows + n1 columns through the L2 of
+                                  one XCD) instead of the default rows kernel + n1 column
+                                  kernel */
 };
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -101,8 +102,8 @@ int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out)
 
 /* As fft3d_plan, with flags: FFT3D_PLAN_HOST_ONLY builds no device state
  * (usable for fft3d_plan_describe / fft3d_plan_twiddles, not for transforms);
- * FFT3D_PLAN_SPLIT_PLANE selects the two-kernel plane step for large planes.
- * The cooperative plane step allocates its counter block (a few KB) here. */
+ * FFT3D_PLAN_COOP_PLANE selects the cooperative plane step for large planes,
+ * which allocates its counter block (some KB) here. */
 int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out);
 
 /* Free a plan and its device table.  NULL is accepted.  The caller must make
@@ -152,9 +153,9 @@ int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream)
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
  * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan's
  * plane step is "fused" when a whole n1 x (n2/2+1) plane fits in LDS (one
- * kernel does both in-plane axes), "coop" for larger planes (one cooperative
- * launch does both), and "split" with FFT3D_PLAN_SPLIT_PLANE (rows kernel +
- * N1 pass); fft3d_plan_describe reports which, and the pass lists of both
+ * kernel does both in-plane axes), "split" for larger planes (rows kernel +
+ * N1 pass), or "coop" with FFT3D_PLAN_COOP_PLANE (one cooperative launch
+ * does both); fft3d_plan_describe reports which, and the pass lists of both
  * directions. */
 enum {
     FFT3D_PASS_PLANE_R2C = 0, /* in: real x; out: spectrum (after the plane step) */

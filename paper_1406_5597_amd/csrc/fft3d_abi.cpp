@@ -185,7 +185,7 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
 {
     if (!out) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: out is NULL");
     *out = nullptr;
-    if (flags & ~(FFT3D_PLAN_HOST_ONLY | FFT3D_PLAN_SPLIT_PLANE))
+    if (flags & ~(FFT3D_PLAN_HOST_ONLY | FFT3D_PLAN_COOP_PLANE))
         return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: unknown flags");
     fft3d_plan_s* h = new (std::nothrow) fft3d_plan_s;
     if (!h) return fail(FFT3D_ERR_NOMEM, "fft3d_plan: out of host memory");

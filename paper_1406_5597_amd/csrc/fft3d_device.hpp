@@ -191,21 +191,28 @@ __device__ __forceinline__ int lds_addr(const LdsLines& L, int w, int i)
 }
 
 // ----------------------------------------------------- XCD-aware order --
-// The hardware hands workgroup b to XCD (b mod 8).  xcd_tile maps workgroup b
-// of a G-workgroup grid to a logical tile so that every XCD works through one
-// contiguous chunk of tiles: neighbouring tiles (which share cache lines at
-// their edges) meet in the same L2.  A bijection on [0, G) for any G; with
-// `reverse`, each chunk is walked from its end (the most recently written
-// data first, when the previous pass wrote the chunks in order).
+// The hardware hands workgroup b to XCD (b mod 8).  Tiles come in groups of g
+// consecutive tiles (e.g. the column tiles of one plane, which share the cache
+// lines at their edges); group_tile sends every group whole to one XCD --
+// group j to XCD (j mod 8) -- so those lines meet in one L2, while the groups
+// in flight at the same time stay neighbours in memory.  The grid is padded to
+// kXcds * g * ceil(groups / kXcds) workgroups; a padding workgroup gets a tile
+// index >= the tile count and leaves.  `reverse` walks the groups of each XCD
+// from the last (the data the previous pass wrote last come first).
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G, bool reverse)
+__host__ __device__ inline int64_t group_grid(int64_t groups, int64_t g)
+{
+    return (int64_t)kXcds * g * ((groups + kXcds - 1) / kXcds);
+}
+
+__device__ __forceinline__ int64_t group_tile(int64_t b, int64_t groups, int64_t g, bool reverse)
 {
     const int64_t x = b % kXcds, k = b / kXcds;
-    const int64_t q = G / kXcds, r = G % kXcds;
-    const int64_t len = q + (x < r ? 1 : 0);
-    const int64_t start = x * q + (x < r ? x : r);
-    return start + (reverse ? len - 1 - k : k);
+    const int64_t per_xcd = (groups + kXcds - 1) / kXcds;
+    int64_t j = k / g;
+    if (reverse) j = per_xcd - 1 - j;
+    return (x + (int64_t)kXcds * j) * g + (k - (k / g) * g);
 }
 
 // ------------------------------------------------------ line accessors --
@@ -216,13 +223,55 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G, bool reverse)
 // the stage driver whether the accessor is the LDS tile (which decides where
 // barriers are needed).
 
+// Column tiles in LDS (lines laid out by LdsLines; linear in the element
+// index, so positions advance by a uniform stride).
 template <typename T> struct LdsIO {
     static constexpr bool kLds = true;
+    static constexpr bool kLinear = true;
     using Pos = int;
     cx<T>* buf;
     LdsLines L;
     __device__ __forceinline__ Pos at(int w, int i) const { return lds_addr(L, w, i); }
     __device__ __forceinline__ Pos adv(Pos p, int d) const { return p + d * L.si; }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return buf[p]; }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const { buf[p] = v; }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+// Rows in LDS with padded positions: element i of row w at w*Hs + pad16(i)
+// (Hs: padded row stride).  Lines along a row.
+template <typename T> struct LdsRowsIO {
+    static constexpr bool kLds = true;
+    static constexpr bool kLinear = false;
+    using Pos = int;
+    cx<T>* buf;
+    int Hs;
+    __device__ __forceinline__ Pos at(int w, int i) const { return w * Hs + pad16(i); }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return buf[p]; }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const { buf[p] = v; }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// The columns of np planes of n1 padded rows in LDS: line w = column
+// (w mod H) of plane (w div H), element i = row i.  Linear in i (stride Hs).
+template <typename T> struct LdsPlaneColsIO {
+    static constexpr bool kLds = true;
+    static constexpr bool kLinear = true;
+    using Pos = int;
+    cx<T>* buf;
+    int H, Hs;
+    int plane;     // n1 * Hs
+    uint32_t mgH;  // div_magic(H)
+    __device__ __forceinline__ Pos at(int w, int i) const
+    {
+        const int p = fdiv(w, mgH);
+        return p * plane + i * Hs + pad16(w - p * H);
+    }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const { return p + d * Hs; }
     __device__ __forceinline__ cx<T> get(Pos p) const { return buf[p]; }
     __device__ __forceinline__ void put(Pos p, cx<T> v) const { buf[p] = v; }
     __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
@@ -293,6 +342,7 @@ template <int SP, typename T> __device__ __forceinline__ void store_cx(cx<T>* p,
 // policies of the loads and stores.
 template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct ColTileIO {
     static constexpr bool kLds = false;
+    static constexpr bool kLinear = true;
     struct Pos {
         int64_t off;  // element offset, column clamped to a valid one
         bool ok;      // the column exists
@@ -330,6 +380,7 @@ template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct ColTileIO {
 // Contiguous lines of `len` elements: line q, element i at q*len + i.
 template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct RowsIO {
     static constexpr bool kLds = false;
+    static constexpr bool kLinear = true;
     using Pos = int;
     const cx<T>* src;
     cx<T>* dst;
@@ -346,6 +397,7 @@ template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct RowsIO {
 // (w div H), element i = row i (stride H).
 template <typename T> struct PlaneColsIO {
     static constexpr bool kLds = false;
+    static constexpr bool kLinear = true;
     using Pos = int;
     const cx<T>* src;
     cx<T>* dst;
@@ -398,9 +450,14 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
         if (b < B) {
             int j, w;
             butterfly_of<R, LINES_FAST>(b, a, j, w);
-            const auto p0 = in.at(w, j);
+            if constexpr (In::kLinear) {
+                const auto p0 = in.at(w, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[k][r] = in.get(in.adv(p0, r * nb));
+                for (int r = 0; r < R; ++r) v[k][r] = in.get(in.adv(p0, r * nb));
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[k][r] = in.ld(w, j + r * nb);
+            }
             if (Ns > 1) {
                 const int m = j - fdiv(j, a.mg_ns) * Ns;
                 const cx<T>* t = tw + m * (R - 1);
@@ -419,9 +476,14 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
             butterfly_of<R, LINES_FAST>(b, a, j, w);
             const int m = j - fdiv(j, a.mg_ns) * Ns;
             const int base = (j - m) * R + m;
-            const auto q0 = out.at(w, base);
+            if constexpr (Out::kLinear) {
+                const auto q0 = out.at(w, base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[k][r]);
+                for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[k][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) out.st(w, base + r * Ns, v[k][r]);
+            }
         }
     }
     if (END) __syncthreads();
@@ -450,18 +512,17 @@ __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines,
 
 // All stages of one axis over `nlines` lines: the first stage reads through
 // `in`, the last writes through `out`, the stages between exchange through
-// the LDS tile `lds`.  in/out may themselves be the LDS tile.  Barriers are
+// the LDS tile `lds`.  mgl = div_magic(nlines) (used when LINES_FAST).  in/out may themselves be the LDS tile.  Barriers are
 // placed from the accessor kinds: a stage that writes LDS ends with one; a
 // stage whose input and output may alias has one between reads and writes.
 // The caller guarantees the tile is ready (barrier) before the call.
 // n == 1 (no stages) is a plain copy from in to out.
-template <bool INV, bool LINES_FAST, int NT, int EPT, typename T, class In, class Out>
-__device__ __forceinline__ void fft_lines(const In& in, const LdsIO<T>& lds, const Out& out, int nlines,
-                                          const AxisSched& S, const cx<T>* __restrict__ tw)
+template <bool INV, bool LINES_FAST, int NT, int EPT, typename T, class In, class Lds, class Out>
+__device__ __forceinline__ void fft_lines(const In& in, const Lds& lds, const Out& out, int nlines,
+                                          uint32_t mgl, const AxisSched& S, const cx<T>* __restrict__ tw)
 {
     constexpr bool IL = In::kLds, OL = Out::kLds;
     const int nst = S.nst;
-    const uint32_t mgl = lds.L.mg_lines;
     if (nst == 0) {  // n == 1: a copy, unless in and out are the same tile
         if (!(IL && OL)) {
             for (int w = (int)threadIdx.x; w < nlines; w += NT) out.st(w, 0, in.ld(w, 0));
@@ -481,7 +542,8 @@ __device__ __forceinline__ void fft_lines(const In& in, const LdsIO<T>& lds, con
 }
 
 // ------------------------------------------------- real <-> half-length --
-// Rows are held as H = h+1 slots (h = n2/2).  The forward split turns the
+// Rows are held as H = h+1 slots (h = n2/2) at padded positions (pad16) of
+// rows Hs apart.  The forward split turns the
 // length-h DFT Z of z[m] = x[2m] + i x[2m+1] into the bins X[0..h] of the
 // real row; the inverse merge does the reverse.  Each thread owns the pair of
 // slots (k, h-k), so both run in place.
@@ -493,7 +555,7 @@ __device__ __forceinline__ void fft_lines(const In& in, const LdsIO<T>& lds, con
 //            Z[0] = (Re X0 + Re Xh) + i (Re X0 - Re Xh)
 //            (the imaginary parts of X[0] and X[h] are never read).
 template <int NT, typename T>
-__device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, int h, uint32_t mg_pairs,
+__device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int Hs, int h, uint32_t mg_pairs,
                                            const cx<T>* __restrict__ post)
 {
     const int npair = h / 2 + 1;  // k = 0 .. h/2
@@ -501,26 +563,26 @@ __device__ __forceinline__ void split_rows(cx<T>* buf, int rows, int rstride, in
     for (int e = (int)threadIdx.x; e < total; e += NT) {
         const int q = fdiv(e, mg_pairs);
         const int k = e - q * npair;
-        cx<T>* Z = buf + q * rstride;
+        cx<T>* Zr = buf + q * Hs;  // row q, element k at Zr[pad16(k)]
         if (k == 0) {
-            cx<T> z0 = Z[0];
-            Z[0] = mk<T>(z0.x + z0.y, (T)0);
-            Z[h] = mk<T>(z0.x - z0.y, (T)0);
+            cx<T> z0 = Zr[pad16(0)];
+            Zr[pad16(0)] = mk<T>(z0.x + z0.y, (T)0);
+            Zr[pad16(h)] = mk<T>(z0.x - z0.y, (T)0);
         } else {
-            cx<T> a = Z[k], b = Z[h - k];
+            cx<T> a = Zr[pad16(k)], b = Zr[pad16(h - k)];
             cx<T> P = mk<T>((T)0.5 * (a.x + b.x), (T)0.5 * (a.y - b.y));
             // (a - conj b) / (2i) = ((a.y + b.y) - i (a.x - b.x)) / 2
             cx<T> O = mk<T>((T)0.5 * (a.y + b.y), (T)-0.5 * (a.x - b.x));
             cx<T> Q = cmul<T>(O, post[k]);
-            Z[k] = cadd<T>(P, Q);
-            if (2 * k != h) Z[h - k] = cconj<T>(csub<T>(P, Q));
+            Zr[pad16(k)] = cadd<T>(P, Q);
+            if (2 * k != h) Zr[pad16(h - k)] = cconj<T>(csub<T>(P, Q));
         }
     }
     __syncthreads();
 }
 
 template <int NT, typename T>
-__device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int rstride, int h, uint32_t mg_pairs,
+__device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int Hs, int h, uint32_t mg_pairs,
                                            const cx<T>* __restrict__ post)
 {
     const int npair = h / 2 + 1;
@@ -528,19 +590,19 @@ __device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int rstride, in
     for (int e = (int)threadIdx.x; e < total; e += NT) {
         const int q = fdiv(e, mg_pairs);
         const int k = e - q * npair;
-        cx<T>* Z = buf + q * rstride;
+        cx<T>* Zr = buf + q * Hs;  // row q, element k at Zr[pad16(k)]
         if (k == 0) {
-            T a0 = Z[0].x, bh = Z[h].x;
-            Z[0] = mk<T>(a0 + bh, a0 - bh);
+            T a0 = Zr[pad16(0)].x, bh = Zr[pad16(h)].x;
+            Zr[pad16(0)] = mk<T>(a0 + bh, a0 - bh);
         } else {
-            cx<T> a = Z[k], b = Z[h - k];
+            cx<T> a = Zr[pad16(k)], b = Zr[pad16(h - k)];
             cx<T> A = mk<T>(a.x + b.x, a.y - b.y);
             cx<T> D = mk<T>(a.x - b.x, a.y + b.y);
             // i * conj(w^k) * D
             cx<T> wD = cmulc<T>(D, post[k]);
             cx<T> Bv = mk<T>(-wD.y, wD.x);
-            Z[k] = cadd<T>(A, Bv);
-            if (2 * k != h) Z[h - k] = cconj<T>(csub<T>(A, Bv));
+            Zr[pad16(k)] = cadd<T>(A, Bv);
+            if (2 * k != h) Zr[pad16(h - k)] = cconj<T>(csub<T>(A, Bv));
         }
     }
     __syncthreads();

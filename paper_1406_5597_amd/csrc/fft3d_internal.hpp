@@ -52,6 +52,8 @@ struct ColPass {
 struct Plan {
     int64_t n0 = 0, n1 = 0, n2 = 0;
     int64_t h = 0, H = 0;     // h = n2/2, H = h+1
+    int Hs = 0;               // padded LDS row stride of the rows kernels
+    int plane_Hs = 0;         // padded LDS row stride of the fused plane kernels
     int64_t C = 0;            // n1*H, columns of the n0 pass
     int64_t M = 0;            // n0*n1*H complex outputs
     int64_t N = 0;            // n0*n1*n2 real inputs

@@ -51,38 +51,61 @@ __device__ __forceinline__ void copy_block(cx<T>* dst, const cx<T>* src, int cou
     }
 }
 
-// LDS view of `rows` rows of H slots (lines along a row).
-// (Lines along a row never need the line-count magic: the row mapping
-// divides by the butterflies per line instead.)
-template <typename T> __device__ __forceinline__ LdsIO<T> lds_rows(cx<T>* buf, int rows, int H)
+// LDS view of `rows` padded rows (lines along a row; see LdsRowsIO).
+template <typename T> __device__ __forceinline__ LdsRowsIO<T> lds_rows(cx<T>* buf, int Hs)
 {
-    LdsIO<T> l;
+    LdsRowsIO<T> l;
     l.buf = buf;
-    l.L.nlines = rows;
-    l.L.lpp = rows;
-    l.L.sp = 0;
-    l.L.sw = H;
-    l.L.si = 1;
-    l.L.mg_lines = 0;
-    l.L.mg_lpp = 0;
+    l.Hs = Hs;
     return l;
 }
 
-// LDS view of the columns of np planes of n1 x H (lines down a column).
+// LDS view of the columns of planes of n1 padded rows (lines down a column).
 template <typename T>
-__device__ __forceinline__ LdsIO<T> lds_plane_cols(cx<T>* buf, int np, int n1, int H, uint32_t mg_lines,
-                                                   uint32_t mgH)
+__device__ __forceinline__ LdsPlaneColsIO<T> lds_plane_cols(cx<T>* buf, int n1, int H, int Hs, uint32_t mgH)
 {
-    LdsIO<T> l;
+    LdsPlaneColsIO<T> l;
     l.buf = buf;
-    l.L.nlines = np * H;
-    l.L.lpp = H;
-    l.L.sp = n1 * H;
-    l.L.sw = 1;
-    l.L.si = H;
-    l.L.mg_lines = mg_lines;
-    l.L.mg_lpp = mgH;
+    l.H = H;
+    l.Hs = Hs;
+    l.plane = n1 * Hs;
+    l.mgH = mgH;
     return l;
+}
+
+// `rows` contiguous rows of H elements in global memory <-> padded LDS rows,
+// 8 loads in flight per thread before the matching stores.  mgH: div_magic(H).
+template <typename T, int NT, int LP = LD_PLAIN>
+__device__ __forceinline__ void rows_to_lds(cx<T>* buf, const cx<T>* src, int rows, int H, int Hs, uint32_t mgH)
+{
+    constexpr int U = 8;
+    const int count = rows * H;
+    for (int base = 0; base < count; base += U * NT) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            v[u] = load_cx<LP, T>(src + (e < count ? e : count - 1));  // always a valid address
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            if (e < count) {
+                const int q = fdiv(e, mgH);
+                buf[q * Hs + pad16(e - q * H)] = v[u];
+            }
+        }
+    }
+}
+
+template <typename T, int NT, int SP = ST_PLAIN>
+__device__ __forceinline__ void lds_to_rows(cx<T>* dst, const cx<T>* buf, int rows, int H, int Hs, uint32_t mgH)
+{
+    const int count = rows * H;
+    for (int e = (int)threadIdx.x; e < count; e += NT) {
+        const int q = fdiv(e, mgH);
+        store_cx<SP, T>(dst + e, buf[q * Hs + pad16(e - q * H)]);
+    }
 }
 
 // ---- tiles: the unit of work of every kernel ----
@@ -108,14 +131,15 @@ __device__ __forceinline__ void col_tile(const cx<T>* src, cx<T>* dst, int64_t S
     l.L.si = W;
     l.L.mg_lines = mg_w;
     l.L.mg_lpp = mg_w;
-    fft_lines<INV, true, NT, EPT, T>(g, l, g, W, ax, tw);
+    fft_lines<INV, true, NT, EPT, T>(g, l, g, W, mg_w, ax, tw);
 }
 
 // `rows` real rows of length n2 (read as h = n2/2 complex values
 // z[m] = x[2m] + i x[2m+1]) -> `rows` rows of H = h+1 bins, contiguous.
-// LP: cache policy of the input loads, SP: of the output stores.
+// Hs: padded LDS row stride.  LP: cache policy of the input loads, SP: of
+// the output stores.
 template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
-__device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int rows, const AxisSched& axh,
+__device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int rows, int Hs, const AxisSched& axh,
                                               const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
                                               cx<T>* buf)
 {
@@ -124,29 +148,29 @@ __device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int ro
     g.src = xz;
     g.dst = nullptr;
     g.len = h;
-    const LdsIO<T> l = lds_rows<T>(buf, rows, H);
-    fft_lines<false, false, NT, EPT, T>(g, l, l, rows, axh, tw);
-    split_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
-    copy_block<T, NT, LD_PLAIN, SP>(Xo, buf, rows * H);
+    const LdsRowsIO<T> l = lds_rows<T>(buf, Hs);
+    fft_lines<false, false, NT, EPT, T>(g, l, l, rows, 0u, axh, tw);
+    split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
+    lds_to_rows<T, NT, SP>(Xo, buf, rows, H, Hs, axh.mg_np1);
 }
 
 // `rows` rows of H bins -> `rows` real rows of length n2.  LP: cache policy
 // of the bin loads, SP: of the output stores.
 template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
-__device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int rows, const AxisSched& axh,
+__device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int rows, int Hs, const AxisSched& axh,
                                               const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
                                               cx<T>* buf)
 {
     const int h = axh.n, H = h + 1;
-    copy_block<T, NT, LP>(buf, Xi, rows * H);
+    rows_to_lds<T, NT, LP>(buf, Xi, rows, H, Hs, axh.mg_np1);
     __syncthreads();
-    merge_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    merge_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
     RowsIO<T, LD_PLAIN, SP> g;
     g.src = nullptr;
     g.dst = yz;
     g.len = h;
-    const LdsIO<T> l = lds_rows<T>(buf, rows, H);
-    fft_lines<true, false, NT, EPT, T>(l, l, g, rows, axh, tw);
+    const LdsRowsIO<T> l = lds_rows<T>(buf, Hs);
+    fft_lines<true, false, NT, EPT, T>(l, l, g, rows, 0u, axh, tw);
 }
 
 // ---- standalone kernels ----
@@ -155,11 +179,12 @@ template <typename T, int NT, int EPT, bool INV>
 __global__ __launch_bounds__(NT) void k_cols(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
                                              const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
                                              int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
-                                             int reverse)
+                                             int64_t ngroups, int gsize, int reverse)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int64_t t = xcd_tile(blockIdx.x, gridDim.x, reverse);
+    const int64_t t = group_tile(blockIdx.x, ngroups, gsize, reverse);
+    if (t >= ngroups * gsize) return;  // padding workgroup
     const int64_t b = t / tiles_per_batch;
     const int64_t c0 = (t - b * tiles_per_batch) * W;
     const int64_t rem = ncols - c0;
@@ -172,16 +197,16 @@ template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
-                                                 int rpw, int reverse)
+                                                 int rpw, int Hs, int reverse)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const AxisSched& axh = *axp;
     const int h = axh.n, H = h + 1;
-    const int64_t row0 = xcd_tile(blockIdx.x, gridDim.x, reverse) * rpw;
+    const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
-    rows_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + row0 * h, X + row0 * H, rows, axh, tw, post,
+    rows_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + row0 * h, X + row0 * H, rows, Hs, axh, tw, post,
                               buf);
 }
 
@@ -190,27 +215,27 @@ template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
-                                                 int rpw, int reverse)
+                                                 int rpw, int Hs, int reverse)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const AxisSched& axh = *axp;
     const int h = axh.n, H = h + 1;
-    const int64_t row0 = xcd_tile(blockIdx.x, gridDim.x, reverse) * rpw;
+    const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
-    rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, axh, tw, post, buf);
+    rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, Hs, axh, tw, post, buf);
 }
 
-// Fused plane forward: ppw whole planes per workgroup, held in LDS as
-// [plane][n1][H]: rows (from HBM), split, then the n1 columns (to HBM).
+// Fused plane forward: ppw whole planes per workgroup, held in LDS as padded
+// rows [plane][n1][Hs]: rows (from HBM), split, then the n1 columns (to HBM).
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axhp,
                                                   const AxisSched* __restrict__ ax1p,
                                                   const cx<T>* __restrict__ tw2,
                                                   const cx<T>* __restrict__ post,
                                                   const cx<T>* __restrict__ tw1, int64_t nplanes,
-                                                  int ppw, uint32_t mg_lines, uint32_t mgH)
+                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -225,17 +250,17 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const Ax
     gi.src = reinterpret_cast<const cx<T>*>(x) + p0 * n1 * h;
     gi.dst = nullptr;
     gi.len = h;
-    const LdsIO<T> lr = lds_rows<T>(buf, rows, H);
-    fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, axh, tw2);
-    split_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
+    fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, 0u, axh, tw2);
+    split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
     PlaneColsIO<T> go;
     go.src = nullptr;
     go.dst = X + p0 * n1 * H;
     go.H = H;
     go.plane = n1 * H;
     go.mgH = mgH;
-    const LdsIO<T> lc = lds_plane_cols<T>(buf, np, n1, H, np == ppw ? mg_lines : div_magic_dev(np * H), mgH);
-    fft_lines<false, true, NT, EPT, T>(lc, lc, go, np * H, ax1, tw1);
+    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
+    fft_lines<false, true, NT, EPT, T>(lc, lc, go, np * H, np == ppw ? mg_lines : div_magic_dev(np * H), ax1, tw1);
 }
 
 // Fused plane inverse: n1 columns (from HBM), merge, rows (to HBM).
@@ -245,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const Ax
                                                   const cx<T>* __restrict__ tw2,
                                                   const cx<T>* __restrict__ post,
                                                   const cx<T>* __restrict__ tw1, int64_t nplanes,
-                                                  int ppw, uint32_t mg_lines, uint32_t mgH)
+                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -262,15 +287,15 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const Ax
     gi.H = H;
     gi.plane = n1 * H;
     gi.mgH = mgH;
-    const LdsIO<T> lc = lds_plane_cols<T>(buf, np, n1, H, np == ppw ? mg_lines : div_magic_dev(np * H), mgH);
-    fft_lines<true, true, NT, EPT, T>(gi, lc, lc, np * H, ax1, tw1);
-    merge_rows<NT, T>(buf, rows, H, h, axh.mg_pairs, post);
+    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
+    fft_lines<true, true, NT, EPT, T>(gi, lc, lc, np * H, np == ppw ? mg_lines : div_magic_dev(np * H), ax1, tw1);
+    merge_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
     RowsIO<T> go;
     go.src = nullptr;
     go.dst = reinterpret_cast<cx<T>*>(y) + p0 * n1 * h;
     go.len = h;
-    const LdsIO<T> lr = lds_rows<T>(buf, rows, H);
-    fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, axh, tw2);
+    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
+    fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, 0u, axh, tw2);
 }
 
 // ---- cooperative plane step for planes larger than LDS ----
@@ -300,6 +325,7 @@ struct CoopArgs {
     int64_t n0;
     int n1, h, H;
     int rpw, RT;         // rows per row task, row tasks per plane
+    int Hs;              // padded LDS row stride
     int W, CT;           // column tile width, column tasks per plane
     uint32_t mg_w;
     int lag;             // L: slots between a plane's two phases
@@ -422,12 +448,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const cx<T>* xz = reinterpret_cast<const cx<T>*>(in) + ((int64_t)pl * n1 + r0) * h;
                 cx<T>* Xo = reinterpret_cast<cx<T>*>(out) + plane + (int64_t)r0 * H;
                 // input read once (streamed); the intermediate stays in L2
-                rows_r2c_tile<T, NT, EPT, LD_STREAM, ST_PLAIN>(xz, Xo, rows, *a.axh, tw2, post, buf);
+                rows_r2c_tile<T, NT, EPT, LD_STREAM, ST_PLAIN>(xz, Xo, rows, a.Hs, *a.axh, tw2, post, buf);
             } else {
                 const cx<T>* Xi = reinterpret_cast<const cx<T>*>(in) + plane + (int64_t)r0 * H;
                 cx<T>* yz = reinterpret_cast<cx<T>*>(out) + ((int64_t)pl * n1 + r0) * h;
                 // the intermediate comes from L2; the output is streamed
-                rows_c2r_tile<T, NT, EPT, LD_L2, ST_STREAM>(Xi, yz, rows, *a.axh, tw2, post, buf);
+                rows_c2r_tile<T, NT, EPT, LD_L2, ST_STREAM>(Xi, yz, rows, a.Hs, *a.axh, tw2, post, buf);
             }
         } else {
             const int c0 = ktask * a.W;
@@ -517,12 +543,12 @@ hipError_t plane_r2c_t(const Plan& p, const void* x, void* X, hipStream_t st)
     if (p.plane_big)
         hipLaunchKernelGGL((k_plane_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, xi,
                            Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
-                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
                            div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
     else
         hipLaunchKernelGGL((k_plane_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
                            xi, Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
-                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
                            div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
     return hipGetLastError();
 }
@@ -537,12 +563,12 @@ hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st)
     if (p.plane_big)
         hipLaunchKernelGGL((k_plane_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, Xi,
                            yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
-                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
                            div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
     else
         hipLaunchKernelGGL((k_plane_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
                            Xi, yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
-                           table<T>(p, p.off_ax1), p.n0, p.ppw,
+                           table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
                            div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
     return hipGetLastError();
 }
@@ -557,10 +583,10 @@ hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int rev, hipStream_
     cx<T>* Xo = static_cast<cx<T>*>(X);
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
-                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
     else
         hipLaunchKernelGGL((k_rows_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, xi,
-                           Xo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+                           Xo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
     return hipGetLastError();
 }
 
@@ -574,10 +600,10 @@ hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int rev, hipStream_
     T* yo = static_cast<T*>(y);
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
     else
         hipLaunchKernelGGL((k_rows_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, rev);
+                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
     return hipGetLastError();
 }
 
@@ -587,17 +613,22 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
 {
     const AxisSched* ax = dsched(p, axis);
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
-    const unsigned grid = (unsigned)(cp.nbatch * cp.tiles_per_batch);
+    // XCD groups: the tiles of one block (plane) for a batched pass, single
+    // tiles for the one-block (n0) pass
+    const int64_t ntiles = cp.nbatch * cp.tiles_per_batch;
+    const int gsize = cp.nbatch > 1 ? (int)cp.tiles_per_batch : 1;
+    const int64_t ngroups = ntiles / gsize;
+    const unsigned grid = (unsigned)group_grid(ngroups, gsize);
     const cx<T>* ci = static_cast<const cx<T>*>(in);
     cx<T>* co = static_cast<cx<T>*>(out);
     if (cp.big)
         hipLaunchKernelGGL((k_cols<T, kNtBig, EB, INV>), dim3(grid), dim3(kNtBig), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
-                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, rev);
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ngroups, gsize, rev);
     else
         hipLaunchKernelGGL((k_cols<T, kNtSmall, ES, INV>), dim3(grid), dim3(kNtSmall), cp.lds, st, ci, co,
                            ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
-                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, rev);
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ngroups, gsize, rev);
     return hipGetLastError();
 }
 
@@ -609,6 +640,7 @@ template <typename T> CoopArgs coop_args(const Plan& p)
     a.h = (int)p.h;
     a.H = (int)p.H;
     a.rpw = p.coop_rpw;
+    a.Hs = p.Hs;
     a.RT = p.coop_rt;
     a.W = p.coop_w;
     a.CT = p.coop_ct;

@@ -60,6 +60,7 @@ bool make_schedule(int64_t n, AxisSched& s)
     s.nst = cnt;
     s.mg_n = div_magic((uint32_t)n);
     s.mg_pairs = div_magic((uint32_t)(n / 2 + 1));
+    s.mg_np1 = div_magic((uint32_t)(n + 1));
     return true;
 }
 
@@ -125,6 +126,17 @@ static void fill_stage_twiddles(const AxisSched& s, long double* out)
 }
 
 // ------------------------------------------------------------- strategy --
+
+// LDS row stride for rows of H elements at padded positions (pad16).  With
+// bank_round the stride is also made 16 mod 32, so that the two rows a wave
+// touches at once in a stage fall in disjoint banks too.
+static int padded_stride(int64_t H, bool bank_round)
+{
+    int m = pad16_host((int)H - 1) + 1;
+    if (bank_round)
+        while (m % 32 != 16) ++m;
+    return m;
+}
 
 static int ilog2(int v)
 {
@@ -231,23 +243,32 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     const int es = kNtSmall * (dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
     const int eb = kNtBig * (dtype ? Tier<double>::kEptBig : Tier<float>::kEptBig);
     const int64_t plane_elems = n1 * p.H;  // >= n1*h: bounds both plane phases
-    const int64_t plane_bytes = plane_elems * cxs;
-    if (plane_elems <= es && plane_bytes <= kLdsHalf) {
+    // a whole plane in LDS as padded rows: bank-friendly stride if it fits,
+    // else the smallest padded stride
+    const int hs_bank = padded_stride(p.H, true), hs_min = padded_stride(p.H, false);
+    p.Hs = hs_bank;
+    bool fused = false;
+    for (int big = 0; big < 2 && !fused; ++big) {
+        const int64_t emax = big ? eb : es, lmax = big ? kLdsMax : kLdsHalf;
+        for (int hs : {hs_bank, hs_min}) {
+            if (plane_elems <= emax && n1 * hs * cxs <= lmax) {
+                fused = true;
+                p.plane_big = big;
+                p.plane_Hs = hs;
+                p.plane_lds = (size_t)(n1 * hs * cxs);
+                break;
+            }
+        }
+    }
+    if (fused) {
         p.fused_plane = true;
-        p.plane_big = false;
         p.ppw = 1;
-        p.plane_lds = (size_t)plane_bytes;
-    } else if (plane_elems <= eb && plane_bytes <= kLdsMax) {
-        p.fused_plane = true;
-        p.plane_big = true;
-        p.ppw = 1;
-        p.plane_lds = (size_t)plane_bytes;
     } else {
         p.fused_plane = false;
-        int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / (p.H * cxs));
+        int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / ((int64_t)p.Hs * cxs));
         p.rows_big = false;
         if (r < 1) {
-            r = std::min<int64_t>(eb / p.h, kLdsMax / (p.H * cxs));
+            r = std::min<int64_t>(eb / p.h, kLdsMax / ((int64_t)p.Hs * cxs));
             p.rows_big = true;
         }
         if (r < 1) {
@@ -255,14 +276,14 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             return FFT3D_ERR_UNSUPPORTED;
         }
         p.rpw = (int)std::min<int64_t>(r, n0 * n1);
-        p.rows_lds = (size_t)(p.rpw * p.H * cxs);
+        p.rows_lds = (size_t)(p.rpw * p.Hs * cxs);
         if (!make_colpass(p.pass1, n1, p.H, p.H, n0, n1 * p.H, cxs, es, eb)) {
             why = "n1 too large for a column tile";
             return FFT3D_ERR_UNSUPPORTED;
         }
         // one cooperative launch for the plane step when both task kinds fit
         // the small tier (and the caller did not ask for the two-kernel path)
-        if (!(flags & FFT3D_PLAN_SPLIT_PLANE) && !p.rows_big && !p.pass1.big && n1 > 1) {
+        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && n1 > 1) {
             p.coop = true;
             p.coop_rpw = p.rpw;
             p.coop_w = p.pass1.W;
@@ -278,7 +299,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             if (const char* lag = getenv("FFT3D_COOP_LAG")) p.coop_lag = std::max(0, atoi(lag));
             p.coop_rt = (int)((n1 + p.coop_rpw - 1) / p.coop_rpw);
             p.coop_ct = (int)((p.H + p.coop_w - 1) / p.coop_w);
-            p.coop_lds = (size_t)std::max<int64_t>(p.coop_rpw * p.H * cxs, n1 * p.coop_w * cxs);
+            p.coop_lds = (size_t)std::max<int64_t>((int64_t)p.coop_rpw * p.Hs * cxs, n1 * p.coop_w * cxs);
         }
     }
     if (!make_colpass(p.pass0, n0, p.C, p.C, 1, 0, cxs, es, eb)) {

@@ -25,7 +25,13 @@ struct AxisSched {
     uint32_t mg_nb[kMaxStages];  // div_magic(n / radix): butterflies per line
     uint32_t mg_n;               // div_magic(n)
     uint32_t mg_pairs;           // div_magic(n/2 + 1): (k, n-k) pairs of a real split
+    uint32_t mg_np1;             // div_magic(n + 1): bins of a real row of length 2n
 };
+
+// Padded position of element i of a row held in LDS: one spare slot after
+// every 16 elements, so the stride-R writes of a Stockham stage fall in
+// different LDS banks.
+inline constexpr int pad16_host(int i) { return i + (i >> 4); }
 
 // Lines in LDS: element i of line w lives at
 //   (w / lpp) * sp + (w % lpp) * sw + i * si.

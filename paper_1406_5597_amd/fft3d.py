@@ -28,7 +28,7 @@ FFT3D_R2C = 0
 FFT3D_C2R = 1
 FFT3D_ROUNDTRIP = 2
 FFT3D_PLAN_HOST_ONLY = 1
-FFT3D_PLAN_SPLIT_PLANE = 2
+FFT3D_PLAN_COOP_PLANE = 2
 FFT3D_PASS_PLANE_R2C = 0
 FFT3D_PASS_N1_FWD = 1
 FFT3D_PASS_N0_FWD = 2
@@ -133,14 +133,14 @@ class Plan:
     """An fft3d plan; owns the C handle (destroyed on close / garbage collection)."""
 
     def __init__(self, n0: int, n1: int, n2: int, dtype: str = "f32", host_only: bool = False,
-                 split_plane: bool = False):
+                 coop_plane: bool = False):
         self.shape = (int(n0), int(n1), int(n2))
         self.dtype = dtype
         dt = {"f32": FFT3D_F32, "f64": FFT3D_F64}.get(dtype)
         if dt is None:
             raise ValueError("dtype must be 'f32' or 'f64'")
         h = ctypes.c_void_p()
-        flags = (FFT3D_PLAN_HOST_ONLY if host_only else 0) | (FFT3D_PLAN_SPLIT_PLANE if split_plane else 0)
+        flags = (FFT3D_PLAN_HOST_ONLY if host_only else 0) | (FFT3D_PLAN_COOP_PLANE if coop_plane else 0)
         _check(lib.fft3d_plan_ex(int(n0), int(n1), int(n2), dt, flags, ctypes.byref(h)))
         self.handle = h.value
 
@@ -198,7 +198,7 @@ def fft3d_plan(n0: int, n1: int, n2: int, dtype: str = "f32") -> Plan:
 
 def fft3d_plan_ex(n0: int, n1: int, n2: int, dtype: str = "f32", flags: int = 0) -> Plan:
     return Plan(n0, n1, n2, dtype, host_only=bool(flags & FFT3D_PLAN_HOST_ONLY),
-                split_plane=bool(flags & FFT3D_PLAN_SPLIT_PLANE))
+                coop_plane=bool(flags & FFT3D_PLAN_COOP_PLANE))
 
 
 def fft3d_plan_destroy(plan: Plan) -> None:

@@ -63,8 +63,9 @@ def test_r2c_c2r_match_oracle(F, oracle, shape, dtype):
     assert rel_l2(host(y3), x * np.prod(shape)) <= TOL[dtype]
 
 
-# planes larger than LDS: the cooperative one-launch plane step (default) and
-# the two-kernel split path share their tile code, so they agree bit for bit
+# planes larger than LDS: the two-kernel split path (default) and the
+# cooperative one-launch plane step share their tile code, so they agree bit
+# for bit
 BIG_PLANES = [(24, 256, 256), (8, 512, 512), (6, 384, 768), (2, 2048, 16), (4, 16, 4096), (6, 512, 96),
               (16, 288, 576), (4, 96, 1536)]
 
@@ -74,8 +75,8 @@ BIG_PLANES = [(24, 256, 256), (8, 512, 512), (6, 384, 768), (2, 2048, 16), (4, 1
 def test_cooperative_plane_step_matches_split_and_oracle(F, oracle, shape, dtype):
     say("coop vs split %s %s" % (shape, dtype))
     x = rounded(fields.uniform(shape, seed=202), dtype)
-    pc = F.Plan(*shape, dtype=dtype)
-    ps = F.Plan(*shape, dtype=dtype, split_plane=True)
+    pc = F.Plan(*shape, dtype=dtype, coop_plane=True)
+    ps = F.Plan(*shape, dtype=dtype)
     if pc.describe()["plane"]["kind"] != "coop":
         pytest.skip("plane fits LDS in %s" % dtype)
     assert ps.describe()["plane"]["kind"] == "split"
