@@ -148,6 +148,33 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     return out, res
 
 
+def kernel_source_sha256() -> str:
+    """Hash of the HIP/C++ sources of the library: a traffic figure measured on
+    other sources is stale."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Per-kernel HBM bytes (FETCH_SIZE and WRITE_SIZE, scaled by the copy
+    calibration) from the committed rocprofv3 summary, if it was taken on the
+    current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "fft3d_512cubed_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+            return rec if rec.get("source_sha256") == kernel_source_sha256() else None
+    return None
+
+
 def copy_bandwidth(torch) -> float:
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
     b = torch.empty_like(a)
@@ -225,6 +252,14 @@ def main() -> int:
             results[d]["rel_l2_c2r"] = fields.rel_l2(yd.cpu().numpy(), yo)
         del Xo, yo
 
+    traffic = recorded_traffic()
+    for d in dtypes:
+        roof = results[d]["roofline"]
+        t = (traffic or {}).get(d, {}).get(roof["kernel"])
+        if t and shape == (512, 512, 512):
+            roof["traffic"] = int(t["fetch_bytes"] + t["write_bytes"])
+            roof["traffic_fetch"] = int(t["fetch_bytes"])
+            roof["traffic_write"] = int(t["write_bytes"])
     head = dtypes[0]
     r = results[head]
     line = {
