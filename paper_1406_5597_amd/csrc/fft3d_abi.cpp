@@ -116,13 +116,22 @@ int enqueue_r2c(const fft3d::Plan& p, const void* x, void* X, hipStream_t s)
         e = fft3d::launch_plane_coop(p, x, X, false, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c cooperative plane kernel");
     } else {
-        e = fft3d::launch_rows_r2c(p, x, X, 0, s);
-        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
-        if (p.n1 > 1) {
-            // each XCD walks its chunk of planes backwards: the planes the rows
-            // kernel wrote last are the most likely to be still cached
-            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, X, X, false, 1, s);
-            if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
+        // planes in groups (all at once by default): rows kernel, then the n1
+        // columns of the same planes, walked backwards so the planes the rows
+        // kernel wrote last come first
+        const int64_t G = p.plane_group > 0 ? p.plane_group : p.n0;
+        for (int64_t g0 = 0; g0 < p.n0; g0 += G) {
+            const int64_t gn = std::min(G, p.n0 - g0);
+            const char* xg = static_cast<const char*>(x) + g0 * p.n1 * p.n2 * p.elem;
+            char* Xg = static_cast<char*>(X) + g0 * p.n1 * p.H * 2 * p.elem;
+            e = fft3d::launch_rows_r2c(p, xg, Xg, gn * p.n1, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
+            if (p.n1 > 1) {
+                fft3d::ColPass cp = p.pass1;
+                cp.nbatch = gn;
+                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, Xg, Xg, false, 1, s);
+                if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
+            }
         }
     }
     if (p.n0 > 1) {
@@ -158,13 +167,23 @@ int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t 
         e = fft3d::launch_plane_coop(p, cur, y, true, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r cooperative plane kernel");
     } else {
-        if (p.n1 > 1) {
-            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, cur, scratch, true, 1, s);
-            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
-            cur = scratch;
+        const int64_t G = p.plane_group > 0 ? p.plane_group : p.n0;
+        for (int64_t g0 = 0; g0 < p.n0; g0 += G) {
+            const int64_t gn = std::min(G, p.n0 - g0);
+            const int64_t off = g0 * p.n1 * p.H * 2 * p.elem;
+            const void* src = static_cast<const char*>(cur) + off;
+            if (p.n1 > 1) {
+                fft3d::ColPass cp = p.pass1;
+                cp.nbatch = gn;
+                void* dst = static_cast<char*>(scratch) + off;
+                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, src, dst, true, 1, s);
+                if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
+                src = dst;
+            }
+            char* yg = static_cast<char*>(y) + g0 * p.n1 * p.n2 * p.elem;
+            e = fft3d::launch_rows_c2r(p, src, yg, gn * p.n1, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
         }
-        e = fft3d::launch_rows_c2r(p, cur, y, 0, s);
-        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
     }
     return FFT3D_OK;
 }
@@ -354,14 +373,14 @@ int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStrea
         if (overlaps(in, rb, out, cb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
         e = p.fused_plane ? fft3d::launch_plane_r2c(p, in, out, s)
             : p.coop      ? fft3d::launch_plane_coop(p, in, out, false, s)
-                          : fft3d::launch_rows_r2c(p, in, out, 0, s);
+                          : fft3d::launch_rows_r2c(p, in, out, p.n0 * p.n1, 0, s);
         break;
     case FFT3D_PASS_PLANE_C2R:
         // the cooperative plane c2r transforms the n1 columns of `in` in place
         if (overlaps(in, cb, out, rb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
         e = p.fused_plane ? fft3d::launch_plane_c2r(p, in, out, s)
             : p.coop      ? fft3d::launch_plane_coop(p, in, out, true, s)
-                          : fft3d::launch_rows_c2r(p, in, out, 0, s);
+                          : fft3d::launch_rows_c2r(p, in, out, p.n0 * p.n1, 0, s);
         break;
     case FFT3D_PASS_N1_FWD:
     case FFT3D_PASS_N1_INV:

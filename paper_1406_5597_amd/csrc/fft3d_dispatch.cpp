@@ -50,13 +50,13 @@ hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t s
 {
     return p.dtype ? launch_plane_c2r_f64(p, X, y, st) : launch_plane_c2r_f32(p, X, y, st);
 }
-hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int rev, hipStream_t st)
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st)
 {
-    return p.dtype ? launch_rows_r2c_f64(p, x, X, rev, st) : launch_rows_r2c_f32(p, x, X, rev, st);
+    return p.dtype ? launch_rows_r2c_f64(p, x, X, nrows, rev, st) : launch_rows_r2c_f32(p, x, X, nrows, rev, st);
 }
-hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int rev, hipStream_t st)
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st)
 {
-    return p.dtype ? launch_rows_c2r_f64(p, X, y, rev, st) : launch_rows_c2r_f32(p, X, y, rev, st);
+    return p.dtype ? launch_rows_c2r_f64(p, X, y, nrows, rev, st) : launch_rows_c2r_f32(p, X, y, nrows, rev, st);
 }
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t st)

@@ -85,6 +85,7 @@ struct Plan {
     int coop_grid = 0;             // set with the device state
     int coop_nslots = 0;
     int coop_lag = 2;              // slots between a plane's two phases
+    int64_t plane_group = 0;       // split plane step in groups of this many planes (0: all at once)
     int64_t coop_ctr_count = 0;
     int* d_ctr = nullptr;
     AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h
@@ -119,8 +120,10 @@ constexpr int kCoopQueues = 16;
     hipError_t launch_plane_coop_##sfx(const Plan& p, const void* in, void* out, bool inverse, hipStream_t s); \
     hipError_t launch_plane_r2c_##sfx(const Plan& p, const void* x, void* X, hipStream_t s);               \
     hipError_t launch_plane_c2r_##sfx(const Plan& p, const void* X, void* y, hipStream_t s);               \
-    hipError_t launch_rows_r2c_##sfx(const Plan& p, const void* x, void* X, int rev, hipStream_t s);       \
-    hipError_t launch_rows_c2r_##sfx(const Plan& p, const void* X, void* y, int rev, hipStream_t s);       \
+    hipError_t launch_rows_r2c_##sfx(const Plan& p, const void* x, void* X, int64_t nrows, int rev,        \
+                                     hipStream_t s);                                                       \
+    hipError_t launch_rows_c2r_##sfx(const Plan& p, const void* X, void* y, int64_t nrows, int rev,        \
+                                     hipStream_t s);                                                       \
     hipError_t launch_cols_##sfx(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, \
                                  void* out, bool inverse, int rev, hipStream_t s);
 FFT3D_DECLARE_DTYPE(f32)
@@ -131,8 +134,9 @@ FFT3D_DECLARE_DTYPE(f64)
 hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
 hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
 // rev: walk each XCD's chunk of tiles from its end (see xcd_tile).
-hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int rev, hipStream_t stream);
-hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int rev, hipStream_t stream);
+// nrows: rows to transform from the given pointers (n0*n1 for a whole array).
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t stream);
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t stream);
 // axis: 0 = n0, 1 = n1 (index into the plan's device schedules).
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t stream);

@@ -13,13 +13,13 @@ hipError_t launch_plane_c2r_f64(const Plan& p, const void* X, void* y, hipStream
 {
     return plane_c2r_t<double>(p, X, y, s);
 }
-hipError_t launch_rows_r2c_f64(const Plan& p, const void* x, void* X, int rev, hipStream_t s)
+hipError_t launch_rows_r2c_f64(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t s)
 {
-    return rows_r2c_t<double>(p, x, X, rev, s);
+    return rows_r2c_t<double>(p, x, X, nrows, rev, s);
 }
-hipError_t launch_rows_c2r_f64(const Plan& p, const void* X, void* y, int rev, hipStream_t s)
+hipError_t launch_rows_c2r_f64(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t s)
 {
-    return rows_c2r_t<double>(p, X, y, rev, s);
+    return rows_c2r_t<double>(p, X, y, nrows, rev, s);
 }
 hipError_t launch_cols_f64(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in,
                            void* out, bool inverse, int rev, hipStream_t s)

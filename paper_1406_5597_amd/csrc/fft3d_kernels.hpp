@@ -227,8 +227,61 @@ __global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const Axi
     rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, Hs, axh, tw, post, buf);
 }
 
-// Fused plane forward: ppw whole planes per workgroup, held in LDS as padded
-// rows [plane][n1][Hs]: rows (from HBM), split, then the n1 columns (to HBM).
+// np whole n1 x n2 planes (np <= ppw) held in LDS as padded rows
+// [plane][n1][Hs]: forward = rows (from HBM), split, then the n1 columns (to
+// HBM); inverse = n1 columns (from HBM), merge, rows (to HBM).  mg_lines =
+// div_magic(np * H).
+template <typename T, int NT, int EPT>
+__device__ __forceinline__ void plane_r2c_tile(const cx<T>* xz, cx<T>* Xo, int np, const AxisSched& axh,
+                                               const AxisSched& ax1, const cx<T>* __restrict__ tw2,
+                                               const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw1,
+                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf)
+{
+    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int rows = np * n1;
+    RowsIO<T> gi;
+    gi.src = xz;
+    gi.dst = nullptr;
+    gi.len = h;
+    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
+    fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, 0u, axh, tw2);
+    split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
+    PlaneColsIO<T> go;
+    go.src = nullptr;
+    go.dst = Xo;
+    go.H = H;
+    go.plane = n1 * H;
+    go.mgH = mgH;
+    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
+    fft_lines<false, true, NT, EPT, T>(lc, lc, go, np * H, mg_lines, ax1, tw1);
+}
+
+template <typename T, int NT, int EPT>
+__device__ __forceinline__ void plane_c2r_tile(const cx<T>* Xi, cx<T>* yz, int np, const AxisSched& axh,
+                                               const AxisSched& ax1, const cx<T>* __restrict__ tw2,
+                                               const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw1,
+                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf)
+{
+    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int rows = np * n1;
+    PlaneColsIO<T> gi;
+    gi.src = Xi;
+    gi.dst = nullptr;
+    gi.H = H;
+    gi.plane = n1 * H;
+    gi.mgH = mgH;
+    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
+    fft_lines<true, true, NT, EPT, T>(gi, lc, lc, np * H, mg_lines, ax1, tw1);
+    merge_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
+    RowsIO<T> go;
+    go.src = nullptr;
+    go.dst = yz;
+    go.len = h;
+    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
+    fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, 0u, axh, tw2);
+}
+
+// Fused plane kernels: ppw whole planes per workgroup.
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axhp,
                                                   const AxisSched* __restrict__ ax1p,
@@ -239,31 +292,14 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const Ax
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const AxisSched& axh = *axhp;
-    const AxisSched& ax1 = *ax1p;
-    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int h = axhp->n, H = h + 1, n1 = ax1p->n;
     const int64_t p0 = (int64_t)blockIdx.x * ppw;
     const int64_t left = nplanes - p0;
     const int np = left < ppw ? (int)left : ppw;
-    const int rows = np * n1;
-    RowsIO<T> gi;
-    gi.src = reinterpret_cast<const cx<T>*>(x) + p0 * n1 * h;
-    gi.dst = nullptr;
-    gi.len = h;
-    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
-    fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, 0u, axh, tw2);
-    split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
-    PlaneColsIO<T> go;
-    go.src = nullptr;
-    go.dst = X + p0 * n1 * H;
-    go.H = H;
-    go.plane = n1 * H;
-    go.mgH = mgH;
-    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
-    fft_lines<false, true, NT, EPT, T>(lc, lc, go, np * H, np == ppw ? mg_lines : div_magic_dev(np * H), ax1, tw1);
+    plane_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + p0 * n1 * h, X + p0 * n1 * H, np, *axhp, *ax1p,
+                               tw2, post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf);
 }
 
-// Fused plane inverse: n1 columns (from HBM), merge, rows (to HBM).
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axhp,
                                                   const AxisSched* __restrict__ ax1p,
@@ -274,28 +310,12 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const Ax
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const AxisSched& axh = *axhp;
-    const AxisSched& ax1 = *ax1p;
-    const int h = axh.n, H = h + 1, n1 = ax1.n;
+    const int h = axhp->n, H = h + 1, n1 = ax1p->n;
     const int64_t p0 = (int64_t)blockIdx.x * ppw;
     const int64_t left = nplanes - p0;
     const int np = left < ppw ? (int)left : ppw;
-    const int rows = np * n1;
-    PlaneColsIO<T> gi;
-    gi.src = X + p0 * n1 * H;
-    gi.dst = nullptr;
-    gi.H = H;
-    gi.plane = n1 * H;
-    gi.mgH = mgH;
-    const LdsPlaneColsIO<T> lc = lds_plane_cols<T>(buf, n1, H, Hs, mgH);
-    fft_lines<true, true, NT, EPT, T>(gi, lc, lc, np * H, np == ppw ? mg_lines : div_magic_dev(np * H), ax1, tw1);
-    merge_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
-    RowsIO<T> go;
-    go.src = nullptr;
-    go.dst = reinterpret_cast<cx<T>*>(y) + p0 * n1 * h;
-    go.len = h;
-    const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
-    fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, 0u, axh, tw2);
+    plane_c2r_tile<T, NT, EPT>(X + p0 * n1 * H, reinterpret_cast<cx<T>*>(y) + p0 * n1 * h, np, *axhp, *ax1p, tw2,
+                               post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf);
 }
 
 // ---- cooperative plane step for planes larger than LDS ----
@@ -574,10 +594,9 @@ hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st)
 }
 
 template <typename T>
-hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int rev, hipStream_t st)
+hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
-    const int64_t nrows = p.n0 * p.n1;
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
     const T* xi = static_cast<const T*>(x);
     cx<T>* Xo = static_cast<cx<T>*>(X);
@@ -591,10 +610,9 @@ hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int rev, hipStream_
 }
 
 template <typename T>
-hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int rev, hipStream_t st)
+hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
-    const int64_t nrows = p.n0 * p.n1;
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
     const cx<T>* Xi = static_cast<const cx<T>*>(X);
     T* yo = static_cast<T*>(y);

@@ -302,6 +302,9 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             p.coop_lds = (size_t)std::max<int64_t>((int64_t)p.coop_rpw * p.Hs * cxs, n1 * p.coop_w * cxs);
         }
     }
+    if (!p.fused_plane && !p.coop) {
+        if (const char* g = getenv("FFT3D_PLANE_GROUP")) p.plane_group = std::max(0, atoi(g));
+    }
     if (!make_colpass(p.pass0, n0, p.C, p.C, 1, 0, cxs, es, eb)) {
         why = "n0 too large for a column tile";
         return FFT3D_ERR_UNSUPPORTED;
