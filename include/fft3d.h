@@ -32,7 +32,11 @@
  *   - every array is device memory owned by the caller; a plan owns only its
  *     twiddle table (device) and its host description;
  *   - fft3d_r2c, fft3d_c2r and fft3d_batch_submit allocate nothing and do
- *     not synchronise: they enqueue kernels on the given stream and return;
+ *     not synchronise: they enqueue kernels on the given stream and return
+ *     (fft3d_batch_submit waits only if its ring slot, 8 launches back, is
+ *     still running); the first plan created on a device also sets up that
+ *     device's batch ring (about 4 MB device + 4 MB pinned host, kept until
+ *     the process ends);
  *   - a plan is immutable after creation and may be used from several
  *     streams or host threads at once, as long as every concurrent call has
  *     its own output and work buffers -- except a plan whose plane step is
@@ -144,10 +148,48 @@ typedef struct {
     void* work;
 } fft3d_batch_item;
 
-/* Enqueue every item on `stream`.  All items are validated first; if any is
- * invalid nothing is enqueued (all or nothing) and the index of the first bad
- * item is in fft3d_last_error().  Items run in order on the stream. */
+/* Run every item in ONE persistent kernel launch on `stream` (the batched
+ * form of the plane step and the strided n0 step, Sec. 2.1-2.2, over many
+ * fields at once).  Each item becomes a chain of passes (the ones fft3d_r2c /
+ * fft3d_c2r would launch); workgroups take tiles of all chains from one
+ * global ticket counter, a pass waiting only for the previous pass of the same
+ * item.  Every result is bit-identical to the item run alone.
+ * Items run CONCURRENTLY: a buffer one item writes (out, mid, work, and in
+ * for C2R without work) must not overlap any buffer of another item; inputs
+ * that are only read may be shared.  Plans must outlive the launch.
+ * All items are validated first; if any is invalid nothing is enqueued (all
+ * or nothing) and fft3d_last_error() names the first bad item.
+ * No allocation: the task list is staged through a ring of pinned/device
+ * buffers set up when the first plan on the device was created (8 launches
+ * deep; a submit that finds its ring slot still in flight waits for it).
+ * Batches of more than 4096 passes are split into several launches. */
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream);
+
+/* flags of fft3d_batch_submit_ex / fft3d_batch_create */
+enum {
+    FFT3D_BATCH_SEQUENTIAL = 2, /* fft3d_batch_submit_ex only: no batched kernel; the items' own kernels,
+                                   item after item (the per-field launch sequence) */
+    FFT3D_BATCH_DIRECT = 4      /* fft3d_batch_create only: launch with hipLaunchKernel instead of a graph */
+};
+int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipStream_t stream);
+
+/* A batch built once and launched many times: the task list and its counters
+ * live in device memory owned by the handle (allocated here, synchronously),
+ * and the launch is a hipGraph of one kernel node (instantiated here) unless
+ * FFT3D_BATCH_DIRECT.  The item pointers are fixed at creation.  The same
+ * concurrency rules as fft3d_batch_submit apply; at most 4096 passes.
+ * Launches of one handle must not overlap in time (same stream, or ordered);
+ * the kernel leaves its counters cleared for the next launch. */
+typedef struct fft3d_batch_s* fft3d_batch_t;
+int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_batch_t* out);
+int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
+/* Error bits of the last finished launch (synchronises the device):
+ * 0 = clean, 1 = a dependency wait hit its spin limit (its tiles skipped). */
+int fft3d_batch_status(fft3d_batch_t b);
+/* JSON: items, tickets, grid, LDS bytes, graph, and the tasks in ticket
+ * order as [kind, dtype, tiles, index of the task waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
+int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len);
+int fft3d_batch_destroy(fft3d_batch_t b);
 
 /* The passes a transform is made of, for fft3d_run_pass.  The forward
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the

@@ -5,19 +5,47 @@
 // forward and inverse transforms.  Nothing here synchronises the device
 // except plan creation, which uploads the twiddle table.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/fft3d.h"
+#include "fft3d_batch_host.hpp"
 #include "fft3d_internal.hpp"
 
 struct fft3d_plan_s {
     fft3d::Plan p;
+};
+
+struct fft3d_batch_s {
+    int nitems = 0;
+    int device = -1;
+    fft3d::BatchTable tab;
+    unsigned grid = 0;
+    void* image = nullptr;  // task image (device)
+    int* ctr = nullptr;     // counter block (device)
+    struct {
+        const fft3d::BatchTask* tasks;
+        const int* firsts;
+        int ntasks;
+        int* ctr;
+        int spin;
+    } args{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~fft3d_batch_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (image) (void)hipFree(image);
+        if (ctr) (void)hipFree(ctr);
+    }
 };
 
 namespace {
@@ -194,6 +222,105 @@ template <typename T> void round_table(const std::vector<long double>& src, std:
     for (size_t i = 0; i < src.size(); ++i) dst[i] = (T)src[i];
 }
 
+// Buffers an item writes and reads, for the cross-item overlap check.
+struct Range {
+    const void* p;
+    size_t n;
+    bool written;
+};
+
+void item_ranges(const fft3d_batch_item& it, std::vector<Range>& r)
+{
+    const fft3d::Plan& p = it.plan->p;
+    const size_t rb = real_bytes(p), cb = cplx_bytes(p);
+    switch (it.dir) {
+    case FFT3D_R2C:
+        r.push_back({it.in, rb, false});
+        r.push_back({it.out, cb, true});
+        break;
+    case FFT3D_C2R:
+        r.push_back({it.in, cb, it.work == nullptr});
+        r.push_back({it.out, rb, true});
+        if (it.work) r.push_back({it.work, cb, true});
+        break;
+    default:
+        r.push_back({it.in, rb, false});
+        r.push_back({it.mid, cb, true});
+        r.push_back({it.out, rb, true});
+        if (it.work) r.push_back({it.work, cb, true});
+        break;
+    }
+}
+
+// Every item valid on its own, and no item writes memory another item uses.
+int validate_batch(const fft3d_batch_item* items, int n, const char* who)
+{
+    if (n < 0 || (n > 0 && !items)) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": bad item array");
+    for (int i = 0; i < n; ++i) {
+        const fft3d_batch_item& it = items[i];
+        int rc;
+        switch (it.dir) {
+        case FFT3D_R2C: rc = validate_r2c(it.plan, it.in, it.out); break;
+        case FFT3D_C2R: rc = validate_c2r(it.plan, it.in, it.out, it.work); break;
+        case FFT3D_ROUNDTRIP:
+            rc = validate_r2c(it.plan, it.in, it.mid);
+            if (!rc) rc = validate_c2r(it.plan, it.mid, it.out, it.work);
+            if (!rc && it.plan && overlaps(it.in, real_bytes(it.plan->p), it.out, real_bytes(it.plan->p)))
+                rc = fail(FFT3D_ERR_INVALID_ARG, "in and out overlap");
+            break;
+        default: rc = fail(FFT3D_ERR_INVALID_ARG, "unknown direction"); break;
+        }
+        if (rc) {
+            char b[96];
+            snprintf(b, sizeof b, "%s: item %d: ", who, i);
+            g_last_error = b + g_last_error;
+            return rc;
+        }
+    }
+    // sweep over the ranges in address order: each range against the ranges
+    // that start before it ends
+    std::vector<Range> all;
+    std::vector<int> owner;
+    for (int i = 0; i < n; ++i) {
+        item_ranges(items[i], all);
+        owner.resize(all.size(), i);
+    }
+    std::vector<size_t> order(all.size());
+    for (size_t a = 0; a < order.size(); ++a) order[a] = a;
+    std::sort(order.begin(), order.end(),
+              [&](size_t a, size_t b) { return (uintptr_t)all[a].p < (uintptr_t)all[b].p; });
+    for (size_t u = 0; u < order.size(); ++u) {
+        const Range& ra = all[order[u]];
+        const uintptr_t end = (uintptr_t)ra.p + ra.n;
+        for (size_t v = u + 1; v < order.size() && (uintptr_t)all[order[v]].p < end; ++v) {
+            const Range& rb = all[order[v]];
+            const int ia = owner[order[u]], ib = owner[order[v]];
+            if (ia != ib && (ra.written || rb.written)) {
+                char m[160];
+                snprintf(m, sizeof m, "%s: item %d writes memory that item %d uses (items run concurrently)", who,
+                         ra.written ? ia : ib, ra.written ? ib : ia);
+                return fail(FFT3D_ERR_INVALID_ARG, m);
+            }
+        }
+    }
+    return FFT3D_OK;
+}
+
+std::vector<fft3d::BatchSpec> batch_specs(const fft3d_batch_item* items, int n)
+{
+    std::vector<fft3d::BatchSpec> v((size_t)n);
+    for (int i = 0; i < n; ++i)
+        v[(size_t)i] = {&items[i].plan->p, items[i].dir, items[i].in, items[i].mid, items[i].out, items[i].work};
+    return v;
+}
+
+// Tuning override of the ticket order (slots between an item's passes).
+int batch_lag_override()
+{
+    const char* v = getenv("FFT3D_BATCH_LAG");
+    return v ? std::max(0, atoi(v)) : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -266,6 +393,11 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
             fft3d_plan_destroy(h);
             return hip_fail(e, "fft3d_plan: schedule upload");
         }
+        e = fft3d::ring_init(dev);
+        if (e != hipSuccess) {
+            fft3d_plan_destroy(h);
+            return fail(FFT3D_ERR_NOMEM, std::string("fft3d_plan: batch ring set-up: ") + hipGetErrorString(e));
+        }
         e = fft3d::coop_setup(h->p);
         if (e != hipSuccess) {
             fft3d_plan_destroy(h);
@@ -321,39 +453,154 @@ int fft3d_c2r(fft3d_plan_t h, void* X, void* y, void* work, hipStream_t s)
 
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
 {
-    if (n < 0 || (n > 0 && !items)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_submit: bad item array");
-    for (int i = 0; i < n; ++i) {
-        const fft3d_batch_item& it = items[i];
-        int rc;
-        switch (it.dir) {
-        case FFT3D_R2C: rc = validate_r2c(it.plan, it.in, it.out); break;
-        case FFT3D_C2R: rc = validate_c2r(it.plan, it.in, it.out, it.work); break;
-        case FFT3D_ROUNDTRIP:
-            rc = validate_r2c(it.plan, it.in, it.mid);
-            if (!rc) rc = validate_c2r(it.plan, it.mid, it.out, it.work);
-            if (!rc && it.plan && overlaps(it.in, real_bytes(it.plan->p), it.out, real_bytes(it.plan->p)))
-                rc = fail(FFT3D_ERR_INVALID_ARG, "in and out overlap");
-            break;
-        default: rc = fail(FFT3D_ERR_INVALID_ARG, "unknown direction"); break;
+    return fft3d_batch_submit_ex(items, n, 0, s);
+}
+
+int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipStream_t s)
+{
+    const char* who = "fft3d_batch_submit";
+    if (flags & ~FFT3D_BATCH_SEQUENTIAL)
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": unknown flags");
+    int rc = validate_batch(items, n, who);
+    if (rc || n == 0) return rc;
+    if (flags & FFT3D_BATCH_SEQUENTIAL) {
+        for (int i = 0; i < n; ++i) {
+            const fft3d_batch_item& it = items[i];
+            if (it.dir == FFT3D_R2C) rc = enqueue_r2c(it.plan->p, it.in, it.out, s);
+            else if (it.dir == FFT3D_C2R) rc = enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
+            else {
+                rc = enqueue_r2c(it.plan->p, it.in, it.mid, s);
+                if (!rc) rc = enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
+            }
+            if (rc) return rc;
         }
-        if (rc) {
-            char b[64];
-            snprintf(b, sizeof b, "fft3d_batch_submit: item %d: ", i);
-            g_last_error = b + g_last_error;
-            return rc;
-        }
+        return FFT3D_OK;
     }
-    for (int i = 0; i < n; ++i) {
-        const fft3d_batch_item& it = items[i];
-        int rc = FFT3D_OK;
-        if (it.dir == FFT3D_R2C) rc = enqueue_r2c(it.plan->p, it.in, it.out, s);
-        else if (it.dir == FFT3D_C2R) rc = enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
-        else {
-            rc = enqueue_r2c(it.plan->p, it.in, it.mid, s);
-            if (!rc) rc = enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
-        }
-        if (rc) return rc;
+    fft3d::BatchOptions o;
+    o.lag = batch_lag_override();
+    // items in chunks whose task lists fit a ring slot (6 passes per item at most)
+    const int chunk = fft3d::kRingTasks / 6;
+    for (int i0 = 0; i0 < n; i0 += chunk) {
+        const int m = std::min(chunk, n - i0);
+        std::vector<fft3d::BatchSpec> specs = batch_specs(items + i0, m);
+        fft3d::BatchTable tab;
+        if (const char* why = fft3d::build_batch_table(specs.data(), m, o, tab))
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
+        const char* why = nullptr;
+        hipError_t e = fft3d::ring_submit(items[0].plan->p.device, tab, s, &why);
+        if (why) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": " + why);
+        if (e != hipSuccess) return hip_fail(e, who);
     }
+    return FFT3D_OK;
+}
+
+int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_batch_t* out)
+{
+    const char* who = "fft3d_batch_create";
+    if (!out) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": out is NULL");
+    *out = nullptr;
+    if (flags & ~FFT3D_BATCH_DIRECT)
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": unknown flags");
+    if (n < 1) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": empty batch");
+    int rc = validate_batch(items, n, who);
+    if (rc) return rc;
+    fft3d::BatchOptions o;
+    o.lag = batch_lag_override();
+    std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
+    if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");
+    b->nitems = n;
+    b->device = items[0].plan->p.device;
+    std::vector<fft3d::BatchSpec> specs = batch_specs(items, n);
+    if (const char* why = fft3d::build_batch_table(specs.data(), n, o, b->tab))
+        return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
+    const int nt = (int)b->tab.tasks.size();
+    if (nt > fft3d::kRingTasks) return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": more than 4096 passes");
+    hipError_t e = fft3d::batch_grid(b->tab, b->device, &b->grid);
+    if (e != hipSuccess) return hip_fail(e, who);
+    const size_t img = fft3d::batch_image_bytes(nt);
+    const size_t ctr = (size_t)(fft3d::kBatchCtrHeader + nt) * sizeof(int);
+    std::vector<char> host(img);
+    fft3d::write_batch_image(b->tab, host.data());
+    if ((e = hipMalloc(&b->image, img)) != hipSuccess || (e = hipMalloc(reinterpret_cast<void**>(&b->ctr), ctr)) != hipSuccess)
+        return fail(FFT3D_ERR_NOMEM, std::string(who) + ": hipMalloc: " + hipGetErrorString(e));
+    if ((e = hipMemcpy(b->image, host.data(), img, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(b->ctr, 0, ctr)) != hipSuccess)
+        return hip_fail(e, who);
+    if (!(flags & FFT3D_BATCH_DIRECT)) {
+        b->args.tasks = reinterpret_cast<const fft3d::BatchTask*>(static_cast<const char*>(b->image) +
+                                                                 fft3d::batch_tasks_offset(nt));
+        b->args.firsts = static_cast<const int*>(b->image);
+        b->args.ntasks = nt;
+        b->args.ctr = b->ctr;
+        b->args.spin = fft3d::kBatchSpinLimit;
+        void* params[] = {&b->args.tasks, &b->args.firsts, &b->args.ntasks, &b->args.ctr, &b->args.spin};
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof kp);
+        kp.func = const_cast<void*>(fft3d::batch_kernel());
+        kp.gridDim = dim3(b->grid);
+        kp.blockDim = dim3(fft3d::kNtSmall);
+        kp.sharedMemBytes = (unsigned)b->tab.lds;
+        kp.kernelParams = params;
+        hipGraphNode_t node;
+        if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess ||
+            (e = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp)) != hipSuccess ||
+            (e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return hip_fail(e, "fft3d_batch_create: graph");
+    }
+    *out = b.release();
+    return FFT3D_OK;
+}
+
+int fft3d_batch_launch(fft3d_batch_t b, hipStream_t s)
+{
+    if (!b) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_launch: batch is NULL");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "fft3d_batch_launch");
+    if (dev != b->device) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_launch: batch belongs to another device");
+    if (b->exec) e = hipGraphLaunch(b->exec, s);
+    else e = fft3d::enqueue_batch_image(b->tab, b->grid, b->image, b->ctr, s);
+    if (e != hipSuccess) return hip_fail(e, "fft3d_batch_launch");
+    return FFT3D_OK;
+}
+
+int fft3d_batch_status(fft3d_batch_t b)
+{
+    if (!b) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_status: batch is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    int v = 0;
+    if (e == hipSuccess) e = hipMemcpy(&v, b->ctr + 3, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "fft3d_batch_status");
+    return v;
+}
+
+int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len)
+{
+    if (!b) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_describe: batch is NULL");
+    static const char* kinds[] = {"plane_r2c", "plane_c2r", "rows_r2c", "rows_c2r", "cols_fwd", "cols_inv"};
+    std::string d = "{\"items\": " + std::to_string(b->nitems) + ", \"tickets\": " + std::to_string(b->tab.tickets) +
+                    ", \"grid\": " + std::to_string(b->grid) + ", \"lds\": " + std::to_string(b->tab.lds) +
+                    ", \"graph\": " +
+                    (b->exec ? "true" : "false") + ", \"tasks\": [";
+    for (size_t i = 0; i < b->tab.tasks.size(); ++i) {
+        const fft3d::BatchTask& t = b->tab.tasks[i];
+        d += (i ? ", " : "");
+        d += "[\"" + std::string(kinds[t.kind]) + "\", \"" + (t.f64 ? "f64" : "f32") + "\", " +
+             std::to_string(t.ntiles) + ", " + std::to_string(t.dep) + ", " + std::to_string(t.lds) + "]";
+    }
+    d += "]}";
+    if (buf && len) {
+        size_t m = std::min(len - 1, d.size());
+        memcpy(buf, d.data(), m);
+        buf[m] = '\0';
+    }
+    return (int)d.size();
+}
+
+int fft3d_batch_destroy(fft3d_batch_t b)
+{
+    if (!b) return FFT3D_OK;
+    delete b;
     return FFT3D_OK;
 }
 

@@ -1,0 +1,201 @@
+// fft3d_batch.hip -- one persistent launch for a whole batch of transforms.
+//
+// Every item of a batch (forward, inverse or both, any supported shape, FP32
+// or FP64) becomes a chain of tasks, one per pass of the single-item path:
+// the plane step (fused, or rows + n1 columns), the strided n0 column pass,
+// and for the inverse the same in reverse order.  The tiles of all tasks are
+// numbered in an order where a task's tiles follow those of the task it
+// depends on; workgroups take the numbers ("tickets") from one global
+// counter, so the kernel runs many small fields at once without a launch per
+// pass and with no idle gap between passes.
+//
+// Dependencies: before its first tile of a task, a workgroup waits until
+// every tile of the task's predecessor has counted itself done, then issues
+// an agent-scope acquire; a finished tile drains its stores, meets the
+// workgroup barrier and counts itself done with an agent-scope release.
+// Every wait is for tiles with smaller tickets than the waiter's, and a
+// ticket is only ever held by a running workgroup, so the smallest
+// unfinished ticket always makes progress: the kernel cannot deadlock,
+// whatever the grid.  Waits are bounded anyway (spin limit); a wait that
+// runs out records an error bit and the tile is skipped, so every workgroup
+// still reaches the end.  The same tile functions as the single-item kernels
+// run the work, with the same schedules, so each result is bit-identical to
+// the item run alone.  All tiles are small-tier (the host picks such
+// tilings), which keeps this one kernel -- every tile kind of both dtypes --
+// quick to compile.
+#include "fft3d_batch.hpp"
+#include "fft3d_kernels.hpp"
+
+namespace fft3d {
+
+template <typename T, int EPT>
+__device__ __forceinline__ void batch_tile(const BatchTask& k, int tile, unsigned char* smem)
+{
+    constexpr int NT = kNtSmall;
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    const cx<T>* t0 = static_cast<const cx<T>*>(k.t0);
+    const cx<T>* t1 = static_cast<const cx<T>*>(k.t1);
+    switch (k.kind) {
+    case kBkPlaneR2C:
+    case kBkPlaneC2R: {
+        const AxisSched& axh = *k.s0;
+        const AxisSched& ax1 = *k.s1;
+        const int h = axh.n, H = h + 1, n1 = ax1.n;
+        const int64_t p0 = (int64_t)tile * k.a0;
+        const int64_t left = k.i0 - p0;
+        const int np = left < k.a0 ? (int)left : k.a0;
+        const uint32_t mg = np == k.a0 ? k.m0 : div_magic_dev(np * H);
+        const cx<T>* t2 = static_cast<const cx<T>*>(k.t2);
+        if (k.kind == kBkPlaneR2C)
+            plane_r2c_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + p0 * n1 * h,
+                                       static_cast<cx<T>*>(k.out) + p0 * n1 * H, np, axh, ax1, t0, t1, t2, k.a1, mg,
+                                       k.m1, buf);
+        else
+            plane_c2r_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + p0 * n1 * H,
+                                       static_cast<cx<T>*>(k.out) + p0 * n1 * h, np, axh, ax1, t0, t1, t2, k.a1, mg,
+                                       k.m1, buf);
+        break;
+    }
+    case kBkRowsR2C:
+    case kBkRowsC2R: {
+        const AxisSched& axh = *k.s0;
+        const int h = axh.n, H = h + 1;
+        const int64_t r0 = (int64_t)tile * k.a0;
+        const int64_t left = k.i0 - r0;
+        const int rows = left < k.a0 ? (int)left : k.a0;
+        if (k.kind == kBkRowsR2C)
+            rows_r2c_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + r0 * h, static_cast<cx<T>*>(k.out) + r0 * H,
+                                      rows, k.a1, axh, t0, t1, buf);
+        else
+            rows_c2r_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + r0 * H, static_cast<cx<T>*>(k.out) + r0 * h,
+                                      rows, k.a1, axh, t0, t1, buf);
+        break;
+    }
+    default: {  // column passes
+        const int W = k.a0;
+        const int b = tile / k.a1;
+        const int64_t c0 = (int64_t)(tile - b * k.a1) * W;
+        const int64_t rem = k.i1 - c0;
+        const int width = rem < (int64_t)W ? (int)rem : W;
+        const int64_t off = (int64_t)b * k.i2 + c0;
+        const cx<T>* src = static_cast<const cx<T>*>(k.in) + off;
+        cx<T>* dst = static_cast<cx<T>*>(k.out) + off;
+        if (k.kind == kBkColsFwd)
+            col_tile<T, NT, EPT, false>(src, dst, k.i0, width, W, k.m0, *k.s0, t0, buf);
+        else
+            col_tile<T, NT, EPT, true>(src, dst, k.i0, width, W, k.m0, *k.s0, t0, buf);
+        break;
+    }
+    }
+}
+
+// Wait until *p >= target; false after `limit` polls, or at once when an
+// earlier wait of the launch has already failed (err != 0), so a failed
+// launch drains quickly.
+__device__ __forceinline__ bool batch_wait(int* p, int target, int* err, int limit)
+{
+    for (int it = 0; it < limit; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+// Every tile of a batch is small-tier (at most 64 KB of data, 80 KB of LDS).
+template <int Unused = 0>
+__global__ __launch_bounds__(kNtSmall) void k_batch(
+    const BatchTask* __restrict__ tasks, const int* __restrict__ firsts, int ntasks, int* ctr, int spin_limit)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_task[3];
+    const int total = firsts[ntasks];
+    int* done = ctr + kBatchCtrHeader;
+    // thread 0's scheduling state
+    int next = 0, cur = 0, checked = -1, failed = -1;
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int t = next;
+            int k = -1, tile = 0, skip = 0;
+            if (t < total) {
+                next = atomicAdd(&ctr[0], 1);  // the next ticket, while this one runs
+                // task of ticket t: firsts[cur] <= t (tickets only grow)
+                if (firsts[cur + 1] <= t) {
+                    int lo = cur + 1, step = 1;
+                    while (lo + step < ntasks && firsts[lo + step] <= t) {
+                        lo += step;
+                        step *= 2;
+                    }
+                    int hi = lo + step < ntasks ? lo + step : ntasks;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (firsts[mid] <= t) lo = mid;
+                        else hi = mid;
+                    }
+                    cur = lo;
+                }
+                k = cur;
+                tile = t - firsts[k];
+                if (k != checked) {
+                    checked = k;
+                    const int dep = tasks[k].dep;
+                    if (dep >= 0) {
+                        if (!batch_wait(&done[dep], tasks[k].dep_tiles, &ctr[1], spin_limit)) {
+                            atomicOr(&ctr[1], kBatchErrWait);
+                            failed = k;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
+                skip = failed == k;
+            }
+            s_task[0] = k;
+            s_task[1] = tile;
+            s_task[2] = skip;
+        }
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_task[0]);
+        const int tile = __builtin_amdgcn_readfirstlane(s_task[1]);
+        const int skip = __builtin_amdgcn_readfirstlane(s_task[2]);
+        if (k < 0) break;
+        const BatchTask& tk = tasks[k];
+        if (!skip) {
+            if (tk.f64) batch_tile<double, Tier<double>::kEptSmall>(tk, tile, smem_raw);
+            else batch_tile<float, Tier<float>::kEptSmall>(tk, tile, smem_raw);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have left for L2
+        __syncthreads();                // ... and every wave's
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        const int prev = __hip_atomic_fetch_add(&ctr[2], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (int)gridDim.x - 1) {
+            // every other workgroup has left: clear the block for the next launch
+            const int err = __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[3], err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < ntasks; ++i) __hip_atomic_store(&done[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[2], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+const void* batch_kernel() { return reinterpret_cast<const void*>(&k_batch<0>); }
+
+hipError_t init_batch() { return allow_lds(k_batch<0>); }
+
+hipError_t batch_occupancy(size_t lds, int* per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_kernel(), kNtSmall, lds);
+}
+
+hipError_t launch_batch(unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts, int ntasks, int* ctr,
+                        int spin_limit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(kNtSmall), lds, s, tasks, firsts, ntasks, ctr, spin_limit);
+    return hipGetLastError();
+}
+
+}  // namespace fft3d

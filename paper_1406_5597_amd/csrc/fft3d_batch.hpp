@@ -1,0 +1,79 @@
+// fft3d_batch.hpp -- the work list of the persistent batched launch.
+//
+// A batch is a list of tasks.  A task is one pass of one item (the plane
+// step, a rows pass, a column pass) cut into tiles; the tiles of a task are
+// independent, and a task may start only once every tile of the task it
+// depends on (the previous pass of the same item) is done.  Tasks are
+// numbered so that a task always comes after the task it depends on, and
+// workgroups take tiles ("tickets") in that order from one global counter.
+// This plain struct is shared by the host builder and the kernel.
+#pragma once
+
+#include <stdint.h>
+
+#include "fft3d_sched.hpp"
+
+namespace fft3d {
+
+enum BatchKind : int32_t {
+    kBkPlaneR2C = 0,  // fused plane step, forward: real planes -> spectrum planes
+    kBkPlaneC2R = 1,  // fused plane step, inverse
+    kBkRowsR2C = 2,   // rows pass of the split plane step, forward
+    kBkRowsC2R = 3,   // rows pass, inverse
+    kBkColsFwd = 4,   // column pass (n1 or n0 axis), forward
+    kBkColsInv = 5,   // column pass, inverse
+};
+
+struct BatchTask {
+    int32_t kind;    // BatchKind
+    int32_t f64;     // 1: FP64 data and tables, 0: FP32
+    int32_t pad0_;
+    int32_t ntiles;  // tiles of this task
+    int32_t dep;     // task this one waits for, or -1
+    int32_t dep_tiles;
+    int32_t lds;  // dynamic LDS bytes the tile needs (host bookkeeping)
+    int32_t pad_;
+    // kind-specific:
+    //  plane: a0 planes per tile, a1 padded LDS row stride, i0 planes,
+    //         m0 div_magic(a0*H), m1 div_magic(H); s0 n2/2 schedule, s1 n1
+    //         schedule; t0 n2/2 twiddles, t1 split roots, t2 n1 twiddles
+    //  rows:  a0 rows per tile, a1 padded LDS row stride, i0 rows;
+    //         s0 n2/2 schedule; t0 n2/2 twiddles, t1 split roots
+    //  cols:  a0 tile width W, a1 tiles per block, i0 row stride S,
+    //         i1 columns per block, i2 block stride, m0 div_magic(W);
+    //         s0 axis schedule; t0 axis twiddles
+    int32_t a0, a1;
+    uint32_t m0, m1;
+    int64_t i0, i1, i2;
+    const void* in;
+    void* out;
+    const AxisSched* s0;
+    const AxisSched* s1;
+    const void* t0;
+    const void* t1;
+    const void* t2;
+};
+
+// Counter block of one batch launch (ints): [ticket, error bits, workgroups
+// finished, status of the last launch, done count of task 0, 1, ...].  The
+// last workgroup to finish clears everything but the status, so the block is
+// ready for the next launch (also when the launch is a graph replay).
+constexpr int kBatchCtrHeader = 4;
+// error bits
+constexpr int kBatchErrWait = 1;  // a dependency wait hit its spin limit
+
+}  // namespace fft3d
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+
+namespace fft3d {
+
+// Device side (fft3d_batch.hip).
+hipError_t init_batch();
+const void* batch_kernel();
+hipError_t batch_occupancy(size_t lds, int* per_cu);
+hipError_t launch_batch(unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts, int ntasks, int* ctr,
+                        int spin_limit, hipStream_t s);
+
+}  // namespace fft3d

@@ -1,0 +1,57 @@
+// fft3d_batch_host.hpp -- host side of the batched launch (fft3d_batch_host.cpp).
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "fft3d_batch.hpp"
+#include "fft3d_internal.hpp"
+
+namespace fft3d {
+
+// One validated item of a batch (pointers as in fft3d_batch_item).
+struct BatchSpec {
+    const Plan* plan;
+    int dir;
+    const void* in;
+    void* mid;
+    void* out;
+    void* work;
+};
+
+struct BatchOptions {
+    // slots between an item's consecutive passes in the ticket order; 0 means
+    // the number of items (pass-major order)
+    int lag = 0;
+};
+
+struct BatchTable {
+    std::vector<BatchTask> tasks;
+    std::vector<int32_t> firsts;  // first ticket of each task, then the total
+    int64_t tickets = 0;
+    size_t lds = 0;  // dynamic LDS of the launch (largest tile)
+};
+
+constexpr int kBatchSpinLimit = 1 << 22;
+constexpr int kRingSlots = 8;     // task images fft3d_batch_submit may have in flight per device
+constexpr int kRingTasks = 4096;  // tasks per ring slot
+
+// Task list of n items; nullptr or why it cannot be built.
+const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions& o, BatchTable& tab);
+// Device image of a task list: firsts, then the tasks (256-byte aligned).
+size_t batch_image_bytes(int ntasks);
+size_t batch_tasks_offset(int ntasks);
+void write_batch_image(const BatchTable& tab, void* dst);
+// Workgroups of the launch: every CU times the workgroups that fit on one,
+// at most one per ticket.
+hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid);
+hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void* dev_image, int* dev_ctr,
+                               hipStream_t s);
+
+// The per-device ring of task images behind fft3d_batch_submit: set up once
+// per device (at plan creation), then each submit stages its image in pinned
+// memory, copies it on the stream and launches, with no allocation.
+hipError_t ring_init(int device);
+hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const char** why);
+
+}  // namespace fft3d

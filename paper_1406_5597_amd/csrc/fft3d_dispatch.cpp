@@ -1,5 +1,6 @@
 // fft3d_dispatch.cpp -- host-side selection of the per-dtype kernel entry
 // points, and the device set-up of the cooperative plane step.
+#include "fft3d_batch.hpp"
 #include "fft3d_internal.hpp"
 
 namespace fft3d {
@@ -34,6 +35,7 @@ hipError_t kernels_init()
     (void)init_plain_f64();
     (void)init_coop_f32();
     (void)init_coop_f64();
+    (void)init_batch();
     (void)hipGetLastError();
     return hipSuccess;
 }

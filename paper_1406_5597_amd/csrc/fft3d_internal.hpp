@@ -102,6 +102,15 @@ struct Plan {
 // FFT3D_* code; `why` receives a message on failure.
 int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why);
 
+// Tiling of the split plane step (rows kernel + n1 column pass) for the
+// plan's shape and dtype, also for plans that fuse the plane step.  Returns
+// nullptr, or why the shape does not fit.
+const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, ColPass& pass1);
+// Small-tier tiling of the column pass along axis 0 (n0, over all C columns)
+// or 1 (n1, per plane): the widest power-of-two W whose tile fits the small
+// tier.  False if not even one column does.
+bool small_colpass(const Plan& p, int axis, ColPass& cp);
+
 // Factor n = 2^a 3^b into stages; false if n has another prime factor.
 bool make_schedule(int64_t n, AxisSched& s);
 

@@ -149,7 +149,7 @@ static int ilog2(int v)
 // columns: aim for rows of >= 128 contiguous bytes, widen for short lines so
 // a tile still carries >= 2048 elements, keep within one tier.
 static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64_t nbatch, int64_t bstride,
-                         int cxs, int es, int eb)
+                         int cxs, int es, int eb, bool allow_big = true)
 {
     cp = ColPass{};
     cp.S = S;
@@ -162,7 +162,10 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     int W = std::min<int64_t>(target, cap);
     while (W < 64 && W < cap && n * W < 2048 && n * W * 2 <= es) W *= 2;
     bool big = false;
-    if (n * W > es) {
+    if (!allow_big) {
+        while (W > 1 && n * W > es) W /= 2;
+        if (n * W > es || n * W * cxs > kLdsHalf) return false;
+    } else if (n * W > es) {
         // prefer the big tier at the target width over narrow segments
         if (n * W <= eb && n * W * cxs <= kLdsMax) {
             big = true;
@@ -181,6 +184,32 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     cp.tiles_per_batch = (ncols + W - 1) / W;
     cp.lds = (size_t)(n * W * cxs);
     return true;
+}
+
+bool small_colpass(const Plan& p, int axis, ColPass& cp)
+{
+    const int cxs = 2 * p.elem;
+    const int es = kNtSmall * (p.dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
+    if (axis == 0) return make_colpass(cp, p.n0, p.C, p.C, 1, 0, cxs, es, es, false);
+    return make_colpass(cp, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, es, false);
+}
+
+const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, ColPass& pass1)
+{
+    const int cxs = 2 * p.elem;
+    const int es = kNtSmall * (p.dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
+    const int eb = kNtBig * (p.dtype ? Tier<double>::kEptBig : Tier<float>::kEptBig);
+    int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / ((int64_t)p.Hs * cxs));
+    rows_big = false;
+    if (r < 1) {
+        r = std::min<int64_t>(eb / p.h, kLdsMax / ((int64_t)p.Hs * cxs));
+        rows_big = true;
+    }
+    if (r < 1) return "n2 too large for one row in LDS";
+    rpw = (int)std::min<int64_t>(r, p.n0 * p.n1);
+    rows_lds = (size_t)(rpw * p.Hs * cxs);
+    if (!make_colpass(pass1, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, eb)) return "n1 too large for a column tile";
+    return nullptr;
 }
 
 int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why)
@@ -265,20 +294,9 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         p.ppw = 1;
     } else {
         p.fused_plane = false;
-        int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / ((int64_t)p.Hs * cxs));
-        p.rows_big = false;
-        if (r < 1) {
-            r = std::min<int64_t>(eb / p.h, kLdsMax / ((int64_t)p.Hs * cxs));
-            p.rows_big = true;
-        }
-        if (r < 1) {
-            why = "n2 too large for one row in LDS";
-            return FFT3D_ERR_UNSUPPORTED;
-        }
-        p.rpw = (int)std::min<int64_t>(r, n0 * n1);
-        p.rows_lds = (size_t)(p.rpw * p.Hs * cxs);
-        if (!make_colpass(p.pass1, n1, p.H, p.H, n0, n1 * p.H, cxs, es, eb)) {
-            why = "n1 too large for a column tile";
+        const char* err = split_tiling(p, p.rpw, p.rows_big, p.rows_lds, p.pass1);
+        if (err) {
+            why = err;
             return FFT3D_ERR_UNSUPPORTED;
         }
         // one cooperative launch for the plane step when both task kinds fit

@@ -35,13 +35,16 @@ FFT3D_PASS_N0_FWD = 2
 FFT3D_PASS_N0_INV = 3
 FFT3D_PASS_N1_INV = 4
 FFT3D_PASS_PLANE_C2R = 5
+FFT3D_BATCH_SEQUENTIAL = 2
+FFT3D_BATCH_DIRECT = 4
 
 # Every symbol include/fft3d.h declares.
 EXPORTS = (
     "fft3d_version", "fft3d_plan", "fft3d_plan_ex", "fft3d_plan_destroy", "fft3d_work_bytes",
     "fft3d_real_bytes", "fft3d_complex_bytes", "fft3d_r2c", "fft3d_c2r", "fft3d_batch_submit",
     "fft3d_strerror", "fft3d_last_error", "fft3d_plan_describe", "fft3d_plan_twiddles",
-    "fft3d_exchange_block", "fft3d_run_pass",
+    "fft3d_exchange_block", "fft3d_run_pass", "fft3d_batch_submit_ex", "fft3d_batch_create",
+    "fft3d_batch_launch", "fft3d_batch_status", "fft3d_batch_describe", "fft3d_batch_destroy",
 )
 
 
@@ -79,6 +82,13 @@ def _load() -> ctypes.CDLL:
         "fft3d_plan_twiddles": (i64, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64]),
         "fft3d_exchange_block": (ctypes.c_int, [i64, i64, i64, i64, i64, ctypes.POINTER(i64)]),
         "fft3d_run_pass": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+        "fft3d_batch_submit_ex": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int, vp]),
+        "fft3d_batch_create": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int,
+                                              ctypes.POINTER(vp)]),
+        "fft3d_batch_launch": (ctypes.c_int, [vp, vp]),
+        "fft3d_batch_status": (ctypes.c_int, [vp]),
+        "fft3d_batch_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
+        "fft3d_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -217,12 +227,75 @@ def fft3d_c2r(plan: Plan, X, y, work=None, stream=None) -> None:
     _check(lib.fft3d_c2r(plan.handle, _addr(X), _addr(y), _addr(work), _stream(stream)))
 
 
-def fft3d_batch_submit(items, stream=None) -> None:
-    """items: sequence of (plan, dir, in, mid, out, work) tuples."""
+def _items(items):
     arr = (BatchItem * max(len(items), 1))()
     for i, (plan, d, a, m, o, w) in enumerate(items):
         arr[i] = BatchItem(plan.handle, d, _addr(a), _addr(m), _addr(o), _addr(w))
-    _check(lib.fft3d_batch_submit(arr, len(items), _stream(stream)))
+    return arr
+
+
+def fft3d_batch_submit(items, stream=None) -> None:
+    """items: sequence of (plan, dir, in, mid, out, work) tuples; one batched launch."""
+    _check(lib.fft3d_batch_submit(_items(items), len(items), _stream(stream)))
+
+
+def fft3d_batch_submit_ex(items, flags: int = 0, stream=None) -> None:
+    _check(lib.fft3d_batch_submit_ex(_items(items), len(items), int(flags), _stream(stream)))
+
+
+class Batch:
+    """A batch built once (task list on the device, hipGraph instantiated) and
+    launched many times; owns the C handle.  Keeps the item tuples (and so the
+    plans and tensors) alive as long as it lives."""
+
+    def __init__(self, items, flags: int = 0):
+        self.items = list(items)
+        h = ctypes.c_void_p()
+        _check(lib.fft3d_batch_create(_items(self.items), len(self.items), int(flags), ctypes.byref(h)))
+        self.handle = h.value
+
+    def launch(self, stream=None) -> None:
+        _check(lib.fft3d_batch_launch(self.handle, _stream(stream)))
+
+    def status(self) -> int:
+        return _check(lib.fft3d_batch_status(self.handle))
+
+    def describe(self) -> dict:
+        n = _check(lib.fft3d_batch_describe(self.handle, None, 0))
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.fft3d_batch_describe(self.handle, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.fft3d_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fft3d_batch_create(items, flags: int = 0) -> Batch:
+    return Batch(items, flags)
+
+
+def fft3d_batch_launch(batch: Batch, stream=None) -> None:
+    batch.launch(stream)
+
+
+def fft3d_batch_status(batch: Batch) -> int:
+    return batch.status()
+
+
+def fft3d_batch_describe(batch: Batch) -> dict:
+    return batch.describe()
+
+
+def fft3d_batch_destroy(batch: Batch) -> None:
+    batch.close()
 
 
 def fft3d_run_pass(plan: Plan, pass_id: int, src, dst, stream=None) -> None:

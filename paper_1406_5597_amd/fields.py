@@ -166,3 +166,18 @@ def rel_l2(a, b) -> float:
     num = np.linalg.norm((a.astype(np.complex128) - b.astype(np.complex128)).ravel())
     den = np.linalg.norm(b.astype(np.complex128).ravel())
     return float(num / den) if den > 0 else float(num)
+
+
+# ---- workload recipes (sizes and mixes; no transform arithmetic) ----
+
+BATCH_SHAPES = ((32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 96, 96), (128, 128, 128), (192, 192, 96))
+
+
+def batch_mix(count: int = 64, seed: int = 4):
+    """The mixed batch: `count` fields, shapes i.i.d. uniform over
+    BATCH_SHAPES, dtype FP32 or FP64 with probability 1/2 each.  Returns a list
+    of (shape, dtype); field i takes its values from uniform(shape, 1000 + i)."""
+    rng = np.random.default_rng(seed)
+    si = rng.integers(0, len(BATCH_SHAPES), size=count)
+    di = rng.integers(0, 2, size=count)
+    return [(BATCH_SHAPES[int(a)], "f64" if int(b) else "f32") for a, b in zip(si, di)]
