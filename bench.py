@@ -148,6 +148,64 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     return out, res
 
 
+def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
+    """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
+    32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
+    1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times one
+    persistent launch of the whole batch (graph replay of a batch handle, and
+    the ring-staged fft3d_batch_submit) against the same items launched field
+    by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL)."""
+    mix = fields.batch_mix(count, seed)
+    plans, items = {}, []
+    b_alg = 0
+    points = 0
+    for i, (shape, dt) in enumerate(mix):
+        if (shape, dt) not in plans:
+            plans[(shape, dt)] = F.Plan(*shape, dtype=dt)
+        p = plans[(shape, dt)]
+        x = torch.from_numpy(fields.as_dtype(fields.uniform(shape, 1000 + i), dt)).to("cuda")
+        items.append((p, F.FFT3D_ROUNDTRIP, x, F.empty_complex(p), F.empty_real(p), F.empty_complex(p)))
+        b_alg += pair_bytes_alg(shape, 4 if dt == "f32" else 8)
+        points += shape[0] * shape[1] * shape[2]
+    s = torch.cuda.current_stream()
+    handle = F.Batch(items)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_graph = timed(lambda: handle.launch(s))
+    ms_ring = timed(lambda: F.fft3d_batch_submit(items, s))
+    ms_seq = timed(lambda: F.fft3d_batch_submit_ex(items, F.FFT3D_BATCH_SEQUENTIAL, s))
+    status = handle.status()
+    desc = handle.describe()
+    gbs = b_alg / (ms_graph * 1e-3) / 1e9
+    return {
+        "workload": "%d fields (seed %d) of %s, FP32/FP64 mixed (%d FP64), %.1f M real points, ROUNDTRIP "
+                    "items" % (count, seed, "/".join("x".join(map(str, sh)) for sh in fields.BATCH_SHAPES),
+                               sum(d == "f64" for _, d in mix), points / 1e6),
+        "fields_s": round(count * 1e3 / ms_graph, 1),
+        "ms_per_launch": round(ms_graph, 4),
+        "ms_ring_submit": round(ms_ring, 4),
+        "ms_per_field_launches": round(ms_seq, 4),
+        "speedup_vs_per_field": round(ms_seq / ms_graph, 3),
+        "B_alg": b_alg,
+        "GB_s_alg": round(gbs, 1),
+        "hbm_frac_alg": round(gbs / HBM_PEAK_GBS, 4),
+        "grid": desc["grid"], "tickets": desc["tickets"], "tasks": len(desc["tasks"]), "lds": desc["lds"],
+        "status": status,
+    }
+
+
 def kernel_source_sha256() -> str:
     """Hash of the HIP/C++ sources of the library: a traffic figure measured on
     other sources is stale."""
@@ -200,6 +258,7 @@ def main() -> int:
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
     ap.add_argument("--coop-plane", action="store_true",
                     help="cooperative one-launch plane step for large planes instead of the two kernels")
     args = ap.parse_args()
@@ -229,6 +288,13 @@ def main() -> int:
             d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
             results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth(torch)
+    batch = None
+    if not args.no_batch:
+        print("# mixed batch ...", file=sys.stderr, flush=True)
+        batch = run_batch(F, torch, fields, args.steps, args.warmup)
+        print("# batch: %.3f ms/launch (%.1f fields/s, %.1f GB/s), per-field launches %.3f ms" % (
+            batch["ms_per_launch"], batch["fields_s"], batch["GB_s_alg"], batch["ms_per_field_launches"]),
+            file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -288,6 +354,7 @@ def main() -> int:
         "plan": r["plan"],
         "cpu_baseline": cpu,
         "copy_GB_s": round(copy_gbs, 1),
+        "batch": batch,
     }
     for k in ("rel_l2_r2c", "rel_l2_c2r"):
         if k in r:

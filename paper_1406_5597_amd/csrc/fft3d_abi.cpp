@@ -31,9 +31,7 @@ struct fft3d_batch_s {
     void* image = nullptr;  // task image (device)
     int* ctr = nullptr;     // counter block (device)
     struct {
-        const fft3d::BatchTask* tasks;
-        const int* firsts;
-        int ntasks;
+        const void* image;
         int* ctr;
         int spin;
     } args{};
@@ -314,11 +312,20 @@ std::vector<fft3d::BatchSpec> batch_specs(const fft3d_batch_item* items, int n)
     return v;
 }
 
-// Tuning override of the ticket order (slots between an item's passes).
-int batch_lag_override()
+// Batch options for a device: its XCDs, and tuning overrides of the ticket
+// order (FFT3D_BATCH_LAG: slots between an item's passes) and of the queue
+// mode (FFT3D_BATCH_MODE: "pinned" or "spread"; default: pinned when that
+// balances the XCDs).
+fft3d::BatchOptions batch_options(int device)
 {
-    const char* v = getenv("FFT3D_BATCH_LAG");
-    return v ? std::max(0, atoi(v)) : 0;
+    fft3d::BatchOptions o;
+    o.xcc_ids = fft3d::device_xcc_ids(device);
+    if (const char* v = getenv("FFT3D_BATCH_LAG")) o.lag = std::max(0, atoi(v));
+    if (const char* v = getenv("FFT3D_BATCH_MODE")) {
+        if (!strcmp(v, "pinned")) o.mode = 1;
+        else if (!strcmp(v, "spread")) o.mode = 2;
+    }
+    return o;
 }
 
 }  // namespace
@@ -476,8 +483,7 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
         }
         return FFT3D_OK;
     }
-    fft3d::BatchOptions o;
-    o.lag = batch_lag_override();
+    fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
     // items in chunks whose task lists fit a ring slot (6 passes per item at most)
     const int chunk = fft3d::kRingTasks / 6;
     for (int i0 = 0; i0 < n; i0 += chunk) {
@@ -504,8 +510,7 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
     if (n < 1) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": empty batch");
     int rc = validate_batch(items, n, who);
     if (rc) return rc;
-    fft3d::BatchOptions o;
-    o.lag = batch_lag_override();
+    fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
     std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
     if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");
     b->nitems = n;
@@ -517,7 +522,7 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
     if (nt > fft3d::kRingTasks) return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": more than 4096 passes");
     hipError_t e = fft3d::batch_grid(b->tab, b->device, &b->grid);
     if (e != hipSuccess) return hip_fail(e, who);
-    const size_t img = fft3d::batch_image_bytes(nt);
+    const size_t img = fft3d::batch_image_bytes(b->tab);
     const size_t ctr = (size_t)(fft3d::kBatchCtrHeader + nt) * sizeof(int);
     std::vector<char> host(img);
     fft3d::write_batch_image(b->tab, host.data());
@@ -527,13 +532,10 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
         (e = hipMemset(b->ctr, 0, ctr)) != hipSuccess)
         return hip_fail(e, who);
     if (!(flags & FFT3D_BATCH_DIRECT)) {
-        b->args.tasks = reinterpret_cast<const fft3d::BatchTask*>(static_cast<const char*>(b->image) +
-                                                                 fft3d::batch_tasks_offset(nt));
-        b->args.firsts = static_cast<const int*>(b->image);
-        b->args.ntasks = nt;
+        b->args.image = b->image;
         b->args.ctr = b->ctr;
         b->args.spin = fft3d::kBatchSpinLimit;
-        void* params[] = {&b->args.tasks, &b->args.firsts, &b->args.ntasks, &b->args.ctr, &b->args.spin};
+        void* params[] = {&b->args.image, &b->args.ctr, &b->args.spin};
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         kp.func = const_cast<void*>(fft3d::batch_kernel());
@@ -569,7 +571,7 @@ int fft3d_batch_status(fft3d_batch_t b)
     if (!b) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_status: batch is NULL");
     hipError_t e = hipDeviceSynchronize();
     int v = 0;
-    if (e == hipSuccess) e = hipMemcpy(&v, b->ctr + 3, sizeof v, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&v, b->ctr + fft3d::kBatchCtrStatus, sizeof v, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "fft3d_batch_status");
     return v;
 }
@@ -580,8 +582,11 @@ int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len)
     static const char* kinds[] = {"plane_r2c", "plane_c2r", "rows_r2c", "rows_c2r", "cols_fwd", "cols_inv"};
     std::string d = "{\"items\": " + std::to_string(b->nitems) + ", \"tickets\": " + std::to_string(b->tab.tickets) +
                     ", \"grid\": " + std::to_string(b->grid) + ", \"lds\": " + std::to_string(b->tab.lds) +
-                    ", \"graph\": " +
-                    (b->exec ? "true" : "false") + ", \"tasks\": [";
+                    ", \"graph\": " + (b->exec ? "true" : "false") + ", \"mode\": \"" +
+                    (b->tab.pinned ? "pinned" : "spread") + "\", \"queue_tickets\": [";
+    for (int q = 0; q < b->tab.nqueues; ++q)
+        d += (q ? ", " : "") + std::to_string(b->tab.queue_tickets[(size_t)q]);
+    d += "], \"tasks\": [";
     for (size_t i = 0; i < b->tab.tasks.size(); ++i) {
         const fft3d::BatchTask& t = b->tab.tasks[i];
         d += (i ? ", " : "");

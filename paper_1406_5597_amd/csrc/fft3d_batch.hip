@@ -102,32 +102,54 @@ __device__ __forceinline__ bool batch_wait(int* p, int target, int* err, int lim
     return false;
 }
 
+__device__ __forceinline__ int image_offset_tasks(int ntasks, int nqueues)
+{
+    const int f = (int)sizeof(BatchHeader) + (ntasks + nqueues) * (int)sizeof(int32_t);
+    return (f + 255) & ~255;
+}
+
 // Every tile of a batch is small-tier (at most 64 KB of data, 80 KB of LDS).
 template <int Unused = 0>
-__global__ __launch_bounds__(kNtSmall) void k_batch(
-    const BatchTask* __restrict__ tasks, const int* __restrict__ firsts, int ntasks, int* ctr, int spin_limit)
+__global__ __launch_bounds__(kNtSmall) void k_batch(const void* __restrict__ image, int* ctr, int spin_limit)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_task[3];
-    const int total = firsts[ntasks];
+    const BatchHeader& hd = *static_cast<const BatchHeader*>(image);
+    const int nqueues = hd.nqueues, ntasks = hd.ntasks, pinned = hd.pinned;
+    const BatchTask* tasks =
+        reinterpret_cast<const BatchTask*>(static_cast<const char*>(image) + image_offset_tasks(ntasks, nqueues));
+    // this workgroup's queue: the one of the XCD it runs on (hardware
+    // register XCC_ID), or the only one
+    const int xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kBatchMaxQueues - 1);
+    const int q = hd.qmap[xcc];
     int* done = ctr + kBatchCtrHeader;
+    int tb = 0, nq = 0;
+    const int* firsts = nullptr;
+    int* ticket = nullptr;
+    if (q >= 0) {
+        tb = hd.task_begin[q];
+        nq = hd.task_begin[q + 1] - tb;
+        firsts = reinterpret_cast<const int*>(&hd + 1) + tb + q;  // nq + 1 entries
+        ticket = ctr + kBatchCtrQueueStride * q;
+    }
+    const int total = q >= 0 ? firsts[nq] : 0;
     // thread 0's scheduling state
     int next = 0, cur = 0, checked = -1, failed = -1;
-    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    if (threadIdx.x == 0 && q >= 0) next = atomicAdd(ticket, 1);
     for (;;) {
         if (threadIdx.x == 0) {
             const int t = next;
             int k = -1, tile = 0, skip = 0;
             if (t < total) {
-                next = atomicAdd(&ctr[0], 1);  // the next ticket, while this one runs
+                next = atomicAdd(ticket, 1);  // the next ticket, while this one runs
                 // task of ticket t: firsts[cur] <= t (tickets only grow)
                 if (firsts[cur + 1] <= t) {
                     int lo = cur + 1, step = 1;
-                    while (lo + step < ntasks && firsts[lo + step] <= t) {
+                    while (lo + step < nq && firsts[lo + step] <= t) {
                         lo += step;
                         step *= 2;
                     }
-                    int hi = lo + step < ntasks ? lo + step : ntasks;
+                    int hi = lo + step < nq ? lo + step : nq;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
                         if (firsts[mid] <= t) lo = mid;
@@ -135,14 +157,14 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(
                     }
                     cur = lo;
                 }
-                k = cur;
-                tile = t - firsts[k];
+                k = tb + cur;
+                tile = t - firsts[cur];
                 if (k != checked) {
                     checked = k;
                     const int dep = tasks[k].dep;
                     if (dep >= 0) {
-                        if (!batch_wait(&done[dep], tasks[k].dep_tiles, &ctr[1], spin_limit)) {
-                            atomicOr(&ctr[1], kBatchErrWait);
+                        if (!batch_wait(&done[dep], tasks[k].dep_tiles, &ctr[kBatchCtrErr], spin_limit)) {
+                            atomicOr(&ctr[kBatchCtrErr], kBatchErrWait);
                             failed = k;
                         }
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -164,22 +186,47 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(
             if (tk.f64) batch_tile<double, Tier<double>::kEptSmall>(tk, tile, smem_raw);
             else batch_tile<float, Tier<float>::kEptSmall>(tk, tile, smem_raw);
         }
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have left for L2
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
         __syncthreads();                // ... and every wave's
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x == 0) {
-        const int prev = __hip_atomic_fetch_add(&ctr[2], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == (int)gridDim.x - 1) {
-            // every other workgroup has left: clear the block for the next launch
-            const int err = __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[3], err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int i = 0; i < ntasks; ++i) __hip_atomic_store(&done[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[2], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            if (pinned) {
+                // the readers of this task's output run on this XCD and read
+                // it through this L2: the drained stores are visible to them
+                __hip_atomic_fetch_add(&done[k], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                // readers may run on any XCD: release (writes back this L2)
+                __hip_atomic_fetch_add(&done[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
+    if (threadIdx.x == 0) {
+        const int prev = __hip_atomic_fetch_add(&ctr[kBatchCtrExit], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (int)gridDim.x - 1) {
+            // every other workgroup has left.  A queue whose tickets were not
+            // all taken had no workgroup on its XCD: its items did not run.
+            int err = __hip_atomic_load(&ctr[kBatchCtrErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int* tables = reinterpret_cast<const int*>(&hd + 1);
+            for (int i = 0; i < nqueues; ++i) {
+                const int b = hd.task_begin[i], n = hd.task_begin[i + 1] - b;
+                const int taken = __hip_atomic_load(&ctr[kBatchCtrQueueStride * i], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                if (taken < tables[b + i + n]) err |= kBatchErrQueue;
+            }
+            // clear the block for the next launch
+            __hip_atomic_store(&ctr[kBatchCtrStatus], err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[kBatchCtrErr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < kBatchMaxQueues; ++i)
+                __hip_atomic_store(&ctr[kBatchCtrQueueStride * i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < ntasks; ++i) __hip_atomic_store(&done[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[kBatchCtrExit], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int Unused = 0> __global__ void k_xcc_probe(int* ids)
+{
+    if (threadIdx.x == 0)
+        ids[blockIdx.x] = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kBatchMaxQueues - 1));
 }
 
 const void* batch_kernel() { return reinterpret_cast<const void*>(&k_batch<0>); }
@@ -191,11 +238,22 @@ hipError_t batch_occupancy(size_t lds, int* per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_kernel(), kNtSmall, lds);
 }
 
-hipError_t launch_batch(unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts, int ntasks, int* ctr,
-                        int spin_limit, hipStream_t s)
+hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, int spin_limit, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(kNtSmall), lds, s, tasks, firsts, ntasks, ctr, spin_limit);
+    hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(kNtSmall), lds, s, image, ctr, spin_limit);
     return hipGetLastError();
+}
+
+hipError_t probe_xcc_ids(int blocks, int* ids)
+{
+    int* d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t)blocks * sizeof(int));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xcc_probe<0>, dim3(blocks), dim3(64), 0, 0, d);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(ids, d, (size_t)blocks * sizeof(int), hipMemcpyDeviceToHost);
+    hipError_t f = hipFree(d);
+    return e != hipSuccess ? e : f;
 }
 
 }  // namespace fft3d

@@ -54,13 +54,38 @@ struct BatchTask {
     const void* t2;
 };
 
-// Counter block of one batch launch (ints): [ticket, error bits, workgroups
-// finished, status of the last launch, done count of task 0, 1, ...].  The
-// last workgroup to finish clears everything but the status, so the block is
-// ready for the next launch (also when the launch is a graph replay).
-constexpr int kBatchCtrHeader = 4;
+// Queues.  A batch has one ticket queue per XCD ("pinned": every task of an
+// item is in the queue of one XCD and only that XCD's workgroups take its
+// tiles, so a pass's output is read back through the same L2 it was written
+// to) or a single queue that every workgroup serves ("spread").
+constexpr int kBatchMaxQueues = 16;
+
+// Head of the device image of a batch, followed by the per-queue ticket
+// tables (queue q: the first ticket of each of its tasks, then its total) and
+// the tasks (queue by queue, task_begin[q] .. task_begin[q+1]-1).
+struct BatchHeader {
+    int32_t nqueues;
+    int32_t pinned;                       // 1: per-XCD queues; 0: one queue
+    int32_t ntasks;
+    int32_t pad0;
+    int32_t qmap[kBatchMaxQueues];        // hardware XCC id -> queue, or -1
+    int32_t task_begin[kBatchMaxQueues + 1];
+    int32_t pad1[3];
+};
+
+// Counter block of one batch launch (ints): the ticket counter of queue q at
+// kBatchCtrQueueStride*q (a 64-byte line each), then error bits, workgroups
+// finished and the status of the last launch, then the done count of every
+// task.  The last workgroup to finish clears everything but the status, so
+// the block is ready for the next launch (also when that is a graph replay).
+constexpr int kBatchCtrQueueStride = 16;
+constexpr int kBatchCtrErr = kBatchMaxQueues * kBatchCtrQueueStride;
+constexpr int kBatchCtrExit = kBatchCtrErr + 1;
+constexpr int kBatchCtrStatus = kBatchCtrErr + 2;
+constexpr int kBatchCtrHeader = kBatchCtrErr + 16;
 // error bits
-constexpr int kBatchErrWait = 1;  // a dependency wait hit its spin limit
+constexpr int kBatchErrWait = 1;   // a dependency wait hit its spin limit
+constexpr int kBatchErrQueue = 2;  // a queue's XCD had no workgroup: its items did not run
 
 }  // namespace fft3d
 
@@ -73,7 +98,10 @@ namespace fft3d {
 hipError_t init_batch();
 const void* batch_kernel();
 hipError_t batch_occupancy(size_t lds, int* per_cu);
-hipError_t launch_batch(unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts, int ntasks, int* ctr,
-                        int spin_limit, hipStream_t s);
+// image: BatchHeader, ticket tables, tasks (see write_batch_image)
+hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, int spin_limit, hipStream_t s);
+// Hardware XCC id of every workgroup of a `blocks`-block probe launch
+// (synchronous; `ids` gets `blocks` values).
+hipError_t probe_xcc_ids(int blocks, int* ids);
 
 }  // namespace fft3d

@@ -57,7 +57,7 @@ const char* item_tiling(const Plan& p, ItemTiling& t)
         t.pass0 = p.pass0;
         if (t.pass0.big && !small_colpass(p, 0, t.pass0)) return "n0 too long for a small-tier column tile";
     }
-    if (p.fused_plane && !p.plane_big) {
+    if (p.fused_plane && !p.plane_big && p.plane_lds <= kBatchLdsCap) {
         t.fused = true;
         t.plane_lds = p.plane_lds;
         t.ppw = p.ppw;
@@ -75,6 +75,13 @@ const char* item_tiling(const Plan& p, ItemTiling& t)
         t.pass1 = p.pass1;
     }
     if (rows_big) return "rows too long for a small-tier tile";
+    // rows per tile within the batch's LDS budget
+    const int64_t row_bytes = (int64_t)p.Hs * 2 * p.elem;
+    if ((int64_t)t.rpw * row_bytes > kBatchLdsCap) {
+        t.rpw = (int)(kBatchLdsCap / row_bytes);
+        if (t.rpw < 1) return "rows too long for a small-tier tile";
+        t.rows_lds = (size_t)(t.rpw * row_bytes);
+    }
     if (p.n1 > 1 && t.pass1.big && !small_colpass(p, 1, t.pass1)) return "n1 too long for a small-tier column tile";
     return nullptr;
 }
@@ -166,6 +173,7 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
 {
     tab = BatchTable{};
     std::vector<std::vector<BatchTask>> chains((size_t)n);
+    std::vector<int64_t> load((size_t)n, 0);
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         const BatchSpec& it = items[i];
@@ -182,58 +190,122 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
             break;
         default: return "unknown direction";
         }
-        for (const BatchTask& t : c) lds = std::max(lds, (size_t)t.lds);
+        for (const BatchTask& t : c) {
+            lds = std::max(lds, (size_t)t.lds);
+            load[(size_t)i] += (int64_t)t.ntiles * t.lds;  // about the bytes the task moves
+        }
     }
-    // order: item i's pass L goes to slot i + L*lag (lag >= n: pass-major,
-    // every item's first pass, then every item's second pass, ...); within a
-    // slot, later passes first.  A pass always lands after its predecessor.
-    struct Key {
-        int64_t slot;
-        int level, item;
-    };
-    std::vector<Key> keys;
-    const int64_t lag = o.lag > 0 ? o.lag : std::max(n, 1);
-    for (int i = 0; i < n; ++i)
-        for (int L = 0; L < (int)chains[(size_t)i].size(); ++L) keys.push_back({i + L * lag, L, i});
-    std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
-        return a.slot != b.slot ? a.slot < b.slot : a.level > b.level;
-    });
+
+    // queues: one per XCD, items placed largest first on the least loaded
+    // (pinned) -- when that balances the XCDs; else one queue (spread)
+    const int nx = (int)o.xcc_ids.size();
+    std::vector<int> queue_of((size_t)n, 0);
+    int nq = 1;
+    bool pinned = false;
+    if (nx > 1 && o.mode != 2 && n > 0) {
+        std::vector<int> order((size_t)n);
+        for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[(size_t)a] > load[(size_t)b]; });
+        std::vector<int64_t> ql((size_t)nx, 0);
+        for (int i : order) {
+            const int best = (int)(std::min_element(ql.begin(), ql.end()) - ql.begin());
+            queue_of[(size_t)i] = best;
+            ql[(size_t)best] += load[(size_t)i];
+        }
+        const int64_t mx = *std::max_element(ql.begin(), ql.end());
+        int64_t sum = 0;
+        for (int64_t v : ql) sum += v;
+        // auto: pin when the busiest XCD has at most 1/4 more than the mean
+        pinned = o.mode == 1 || (int64_t)4 * nx * mx <= (int64_t)5 * sum;
+        if (pinned) nq = nx;
+    }
+    if (!pinned) std::fill(queue_of.begin(), queue_of.end(), 0);
+    tab.nqueues = nq;
+    tab.pinned = pinned;
+    for (int x = 0; x < kBatchMaxQueues; ++x) tab.qmap[x] = pinned ? -1 : 0;
+    if (pinned)
+        for (int qi = 0; qi < nx; ++qi) tab.qmap[o.xcc_ids[(size_t)qi] & (kBatchMaxQueues - 1)] = qi;
+
+    // order within a queue: item i's pass L goes to slot r + L*lag, r the
+    // item's rank in its queue (lag >= items: pass-major, every item's first
+    // pass, then every item's second pass, ...); within a slot, later passes
+    // first.  A pass always lands after its predecessor.
     std::vector<std::vector<int>> index((size_t)n);
     for (int i = 0; i < n; ++i) index[(size_t)i].assign(chains[(size_t)i].size(), -1);
-    int64_t tickets = 0;
-    for (const Key& k : keys) {
-        BatchTask t = chains[(size_t)k.item][(size_t)k.level];
-        if (k.level > 0) {
-            const int d = index[(size_t)k.item][(size_t)k.level - 1];
-            if (d < 0) return "internal error: a pass ordered before its predecessor";
-            t.dep = d;
-            t.dep_tiles = tab.tasks[(size_t)d].ntiles;
+    tab.task_begin.assign((size_t)nq + 1, 0);
+    tab.queue_tickets.assign((size_t)nq, 0);
+    for (int qi = 0; qi < nq; ++qi) {
+        struct Key {
+            int64_t slot;
+            int level, item;
+        };
+        std::vector<Key> keys;
+        int rank = 0;
+        int nitems = 0;
+        for (int i = 0; i < n; ++i) nitems += queue_of[(size_t)i] == qi;
+        const int64_t lag = o.lag > 0 ? o.lag : std::max(nitems, 1);
+        for (int i = 0; i < n; ++i) {
+            if (queue_of[(size_t)i] != qi) continue;
+            for (int L = 0; L < (int)chains[(size_t)i].size(); ++L) keys.push_back({rank + L * lag, L, i});
+            ++rank;
         }
-        index[(size_t)k.item][(size_t)k.level] = (int)tab.tasks.size();
+        std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+            return a.slot != b.slot ? a.slot < b.slot : a.level > b.level;
+        });
+        tab.task_begin[(size_t)qi] = (int)tab.tasks.size();
+        int64_t tickets = 0;
+        for (const Key& k : keys) {
+            BatchTask t = chains[(size_t)k.item][(size_t)k.level];
+            if (k.level > 0) {
+                const int d = index[(size_t)k.item][(size_t)k.level - 1];
+                if (d < 0) return "internal error: a pass ordered before its predecessor";
+                t.dep = d;
+                t.dep_tiles = tab.tasks[(size_t)d].ntiles;
+            }
+            index[(size_t)k.item][(size_t)k.level] = (int)tab.tasks.size();
+            tab.firsts.push_back((int32_t)tickets);
+            tickets += t.ntiles;
+            if (tickets > 0x3fffffff) return "too many tiles in one batch";
+            tab.tasks.push_back(t);
+        }
         tab.firsts.push_back((int32_t)tickets);
-        tickets += t.ntiles;
-        if (tickets > 0x3fffffff) return "too many tiles in one batch";
-        tab.tasks.push_back(t);
+        tab.queue_tickets[(size_t)qi] = tickets;
+        tab.tickets += tickets;
     }
-    tab.firsts.push_back((int32_t)tickets);
-    tab.tickets = tickets;
+    tab.task_begin[(size_t)nq] = (int)tab.tasks.size();
     tab.lds = lds;
     return nullptr;
 }
 
-size_t batch_image_bytes(int ntasks)
+size_t batch_tasks_offset(int ntasks, int nqueues)
 {
-    const size_t f = ((size_t)(ntasks + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
-    return f + (size_t)ntasks * sizeof(BatchTask);
+    return (sizeof(BatchHeader) + (size_t)(ntasks + nqueues) * sizeof(int32_t) + 255) & ~(size_t)255;
 }
 
-size_t batch_tasks_offset(int ntasks) { return ((size_t)(ntasks + 1) * sizeof(int32_t) + 255) & ~(size_t)255; }
+size_t batch_image_bytes(int ntasks, int nqueues)
+{
+    return batch_tasks_offset(ntasks, nqueues) + (size_t)ntasks * sizeof(BatchTask);
+}
+
+size_t batch_image_bytes(const BatchTable& tab)
+{
+    return batch_image_bytes((int)tab.tasks.size(), tab.nqueues);
+}
 
 void write_batch_image(const BatchTable& tab, void* dst)
 {
     const int nt = (int)tab.tasks.size();
-    memcpy(dst, tab.firsts.data(), (size_t)(nt + 1) * sizeof(int32_t));
-    memcpy(static_cast<char*>(dst) + batch_tasks_offset(nt), tab.tasks.data(), (size_t)nt * sizeof(BatchTask));
+    BatchHeader h;
+    memset(&h, 0, sizeof h);
+    h.nqueues = tab.nqueues;
+    h.pinned = tab.pinned ? 1 : 0;
+    h.ntasks = nt;
+    for (int x = 0; x < kBatchMaxQueues; ++x) h.qmap[x] = tab.qmap[x];
+    for (int q = 0; q <= tab.nqueues; ++q) h.task_begin[q] = tab.task_begin[(size_t)q];
+    char* d = static_cast<char*>(dst);
+    memcpy(d, &h, sizeof h);
+    memcpy(d + sizeof h, tab.firsts.data(), tab.firsts.size() * sizeof(int32_t));
+    memcpy(d + batch_tasks_offset(nt, tab.nqueues), tab.tasks.data(), (size_t)nt * sizeof(BatchTask));
 }
 
 hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
@@ -247,7 +319,9 @@ hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
         const int w = atoi(v);
         if (w >= 1 && w <= std::max(per_cu, 1)) g = (int64_t)cus * w;
     }
-    g = std::min<int64_t>(g, std::max<int64_t>(tab.tickets, 1));
+    // one queue: no more workgroups than tickets; per-XCD queues: every XCD
+    // must get workgroups (blocks go to the XCDs in turn), so keep them all
+    if (!tab.pinned) g = std::min<int64_t>(g, std::max<int64_t>(tab.tickets, 1));
     *grid = (unsigned)g;
     return hipSuccess;
 }
@@ -255,11 +329,7 @@ hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
 hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void* dev_image, int* dev_ctr,
                                hipStream_t s)
 {
-    const int nt = (int)tab.tasks.size();
-    const int* firsts = static_cast<const int*>(dev_image);
-    const BatchTask* tasks =
-        reinterpret_cast<const BatchTask*>(static_cast<const char*>(dev_image) + batch_tasks_offset(nt));
-    return launch_batch(grid, tab.lds, tasks, firsts, nt, dev_ctr, kBatchSpinLimit, s);
+    return launch_batch(grid, tab.lds, dev_image, dev_ctr, kBatchSpinLimit, s);
 }
 
 // ---------------------------------------------------------------- ring --
@@ -277,6 +347,7 @@ struct Slot {
 struct Ring {
     int device = -1;
     int next = 0;
+    std::vector<int> xcc_ids;  // distinct hardware XCC ids of the device
     Slot slots[kRingSlots];
     std::mutex mu;
 };
@@ -301,7 +372,14 @@ hipError_t ring_init(int device)
         if (r->device == device) return hipSuccess;
     std::unique_ptr<Ring> r(new Ring);
     r->device = device;
-    const size_t img = batch_image_bytes(kRingTasks);
+    // the XCDs the device dispatches to (a probe launch of 1024 workgroups)
+    std::vector<int> ids(1024);
+    hipError_t pe = probe_xcc_ids(1024, ids.data());
+    if (pe != hipSuccess) return pe;
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    r->xcc_ids = ids;
+    const size_t img = batch_image_bytes(kRingTasks, kBatchMaxQueues);
     const size_t ctr = (size_t)(kBatchCtrHeader + kRingTasks) * sizeof(int);
     for (Slot& s : r->slots) {
         hipError_t e = hipHostMalloc(&s.host, img, hipHostMallocDefault);
@@ -321,6 +399,12 @@ hipError_t ring_init(int device)
     }
     g_rings.push_back(std::move(r));
     return hipSuccess;
+}
+
+std::vector<int> device_xcc_ids(int device)
+{
+    Ring* r = ring_of(device);
+    return r ? r->xcc_ids : std::vector<int>();
 }
 
 hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const char** why)
@@ -345,7 +429,7 @@ hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const c
     // (normally long since: the ring is kRingSlots deep)
     if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return e;
     write_batch_image(tab, sl.host);
-    const size_t bytes = batch_image_bytes((int)tab.tasks.size());
+    const size_t bytes = batch_image_bytes(tab);
     e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = enqueue_batch_image(tab, grid, sl.dev, sl.ctr, s);
     if (e == hipSuccess) e = hipEventRecord(sl.done, s);

@@ -20,27 +20,44 @@ struct BatchSpec {
 };
 
 struct BatchOptions {
+    // the device's hardware XCC ids (one queue per XCD when pinned)
+    std::vector<int> xcc_ids;
+    // 0: pin items to XCDs when that balances them, else one queue;
+    // 1: always pin; 2: never pin
+    int mode = 0;
     // slots between an item's consecutive passes in the ticket order; 0 means
     // the number of items (pass-major order)
     int lag = 0;
 };
 
 struct BatchTable {
-    std::vector<BatchTask> tasks;
-    std::vector<int32_t> firsts;  // first ticket of each task, then the total
+    std::vector<BatchTask> tasks;  // queue by queue
+    // per queue: the first ticket (within the queue) of each of its tasks,
+    // then its total; queue q's entries start at task_begin[q] + q
+    std::vector<int32_t> firsts;
+    std::vector<int> task_begin;         // nqueues + 1
+    std::vector<int64_t> queue_tickets;  // nqueues
+    int nqueues = 1;
+    bool pinned = false;
+    int qmap[kBatchMaxQueues] = {};
     int64_t tickets = 0;
     size_t lds = 0;  // dynamic LDS of the launch (largest tile)
 };
 
-constexpr int kBatchSpinLimit = 1 << 22;
+constexpr int kBatchSpinLimit = 1 << 20;
+// LDS of one batch tile: half a CU's LDS less the kernel's own few words, so
+// that two workgroups fit on a CU.
+constexpr int64_t kBatchLdsCap = kLdsHalf - 256;
 constexpr int kRingSlots = 8;     // task images fft3d_batch_submit may have in flight per device
 constexpr int kRingTasks = 4096;  // tasks per ring slot
 
 // Task list of n items; nullptr or why it cannot be built.
 const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions& o, BatchTable& tab);
-// Device image of a task list: firsts, then the tasks (256-byte aligned).
-size_t batch_image_bytes(int ntasks);
-size_t batch_tasks_offset(int ntasks);
+// Device image of a task list: BatchHeader, the per-queue ticket tables, then
+// the tasks (256-byte aligned).
+size_t batch_image_bytes(int ntasks, int nqueues);
+size_t batch_image_bytes(const BatchTable& tab);
+size_t batch_tasks_offset(int ntasks, int nqueues);
 void write_batch_image(const BatchTable& tab, void* dst);
 // Workgroups of the launch: every CU times the workgroups that fit on one,
 // at most one per ticket.
@@ -52,6 +69,8 @@ hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void*
 // per device (at plan creation), then each submit stages its image in pinned
 // memory, copies it on the stream and launches, with no allocation.
 hipError_t ring_init(int device);
+// Distinct hardware XCC ids of the device (found by ring_init), or empty.
+std::vector<int> device_xcc_ids(int device);
 hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const char** why);
 
 }  // namespace fft3d

@@ -1,0 +1,331 @@
+// batch_sim.cpp -- CPU check of the batched launch's task lists and of its
+// ticket protocol (test infrastructure; built by tests/test_batch_host.py).
+//
+// Reads items from stdin, one per line: "n0 n1 n2 dtype dir work" (dtype 0
+// FP32 / 1 FP64, dir 0 R2C / 1 C2R / 2 ROUNDTRIP, work 0/1), and optional
+// lines "lag L", "mode M" (0 auto, 1 pinned, 2 spread), "xcds X" (the device
+// has XCC ids 0..X-1; default 8).  Builds host-only plans and the batch's
+// task list with the library's own host code (fake, disjoint device
+// addresses), then:
+//  1. checks the table: tickets numbered in order, every task after the task
+//     it waits for (the previous pass of its item), tile LDS within budget;
+//  2. checks every tile's memory footprint (the index arithmetic the kernel
+//     uses) against the item's buffers;
+//  3. runs the kernel's scheduling loop -- a ticket counter per queue, the
+//     next ticket taken before the current tile runs, the task found by a
+//     galloping search, a wait for the dependency before a task's first tile
+//     -- on G host threads (thread g on XCD g mod X, as blocks are dealt to
+//     the XCDs in turn), and checks that it ends with every tile run exactly
+//     once, after all tiles of its dependency, and, when items are pinned,
+//     with every pass of an item on the item's XCD.
+// Prints "ok <tasks> <tickets> <lds> <pinned>" or "FAIL: why" (exit 1).
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <chrono>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../include/fft3d.h"
+#include "../paper_1406_5597_amd/csrc/fft3d_batch_host.hpp"
+
+using namespace fft3d;
+
+// The device half of the library is not linked: these are never called.
+namespace fft3d {
+hipError_t batch_occupancy(size_t, int* per_cu)
+{
+    *per_cu = 1;
+    return hipSuccess;
+}
+hipError_t launch_batch(unsigned, size_t, const void*, int*, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t probe_xcc_ids(int, int*) { return hipErrorNotSupported; }
+}  // namespace fft3d
+
+static int fail(const std::string& m)
+{
+    printf("FAIL: %s\n", m.c_str());
+    return 1;
+}
+
+struct Buf {
+    uintptr_t base;
+    size_t bytes;
+};
+
+struct ItemBufs {
+    Buf in, mid, out, work;
+};
+
+static bool inside(uintptr_t a, size_t n, const Buf& b) { return b.base && a >= b.base && a + n <= b.base + b.bytes; }
+
+// Byte range [lo, hi) of `count` elements at element offset `off` with
+// stride 1, of `es` bytes each, from `ptr`.
+static void span(const void* ptr, int64_t off, int64_t count, int es, uintptr_t& lo, size_t& n)
+{
+    lo = (uintptr_t)ptr + (uintptr_t)(off * es);
+    n = (size_t)(count * es);
+}
+
+int main(int argc, char** argv)
+{
+    int G = argc > 1 ? atoi(argv[1]) : 64;
+    std::vector<Plan> plans;
+    std::vector<int> dirs, works;
+    BatchOptions o;
+    int xcds = 8;
+    char line[256];
+    while (fgets(line, sizeof line, stdin)) {
+        long long n0, n1, n2;
+        int dt, dir, work;
+        int lag;
+        if (sscanf(line, "lag %d", &lag) == 1) {
+            o.lag = lag;
+            continue;
+        }
+        if (sscanf(line, "mode %d", &lag) == 1) {
+            o.mode = lag;
+            continue;
+        }
+        if (sscanf(line, "xcds %d", &lag) == 1) {
+            xcds = lag;
+            continue;
+        }
+        if (sscanf(line, "%lld %lld %lld %d %d %d", &n0, &n1, &n2, &dt, &dir, &work) != 6) continue;
+        Plan p;
+        std::string why;
+        if (plan_build_host(p, n0, n1, n2, dt, 0, why)) return fail("plan: " + why);
+        plans.push_back(p);
+        dirs.push_back(dir);
+        works.push_back(work);
+    }
+    const int n = (int)plans.size();
+    // fake device memory: every plan's tables and every buffer disjoint
+    uintptr_t next = 1ull << 32;
+    auto take = [&](size_t bytes) {
+        uintptr_t a = next;
+        next += (bytes + 4095) / 4096 * 4096 + 4096;
+        return a;
+    };
+    std::vector<ItemBufs> bufs((size_t)n);
+    std::vector<BatchSpec> specs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        Plan& p = plans[(size_t)i];
+        p.d_sched = reinterpret_cast<AxisSched*>(take(3 * sizeof(AxisSched)));
+        p.d_tw = reinterpret_cast<void*>(take((size_t)p.tw_count * 2 * p.elem));
+        p.has_device = true;
+        const size_t rb = (size_t)p.N * p.elem, cb = (size_t)p.M * 2 * p.elem;
+        ItemBufs& b = bufs[(size_t)i];
+        memset(&b, 0, sizeof b);
+        if (dirs[(size_t)i] == FFT3D_C2R) {
+            b.in = {take(cb), cb};
+            b.out = {take(rb), rb};
+        } else if (dirs[(size_t)i] == FFT3D_R2C) {
+            b.in = {take(rb), rb};
+            b.out = {take(cb), cb};
+        } else {
+            b.in = {take(rb), rb};
+            b.mid = {take(cb), cb};
+            b.out = {take(rb), rb};
+        }
+        if (works[(size_t)i] && dirs[(size_t)i] != FFT3D_R2C) b.work = {take(cb), cb};
+        specs[(size_t)i] = {&p, dirs[(size_t)i], (const void*)b.in.base, (void*)b.mid.base, (void*)b.out.base,
+                            (void*)b.work.base};
+    }
+    for (int x = 0; x < xcds; ++x) o.xcc_ids.push_back(x);
+    BatchTable tab;
+    if (const char* why = build_batch_table(specs.data(), n, o, tab)) return fail(why);
+    const int nt = (int)tab.tasks.size();
+    const int nq = tab.nqueues;
+
+    // 1. the table
+    if ((int)tab.task_begin.size() != nq + 1 || tab.task_begin[0] != 0 || tab.task_begin[(size_t)nq] != nt)
+        return fail("queue task ranges");
+    if ((int)tab.firsts.size() != nt + nq) return fail("ticket table size");
+    std::vector<int> qof((size_t)nt, -1);
+    int64_t all = 0;
+    for (int q = 0; q < nq; ++q) {
+        const int b = tab.task_begin[(size_t)q], e = tab.task_begin[(size_t)q + 1];
+        const int32_t* f = tab.firsts.data() + b + q;
+        if (f[0] != 0) return fail("queue tickets do not start at 0");
+        for (int k = b; k < e; ++k) {
+            qof[(size_t)k] = q;
+            const BatchTask& t = tab.tasks[(size_t)k];
+            if (t.ntiles < 1) return fail("empty task");
+            if (f[k - b + 1] - f[k - b] != t.ntiles) return fail("ticket table does not count tiles");
+            if (t.dep >= 0 && (t.dep < b || t.dep >= k)) return fail("task waits for a later task or another queue");
+            if (t.dep >= 0 && t.dep_tiles != tab.tasks[(size_t)t.dep].ntiles) return fail("dep_tiles");
+            if ((size_t)t.lds > tab.lds || (int64_t)tab.lds > kBatchLdsCap) return fail("LDS over budget");
+        }
+        if (f[e - b] != tab.queue_tickets[(size_t)q]) return fail("queue total");
+        all += f[e - b];
+    }
+    if (all != tab.tickets) return fail("ticket total");
+    if (tab.pinned ? nq != xcds : nq != 1) return fail("queue count");
+    for (int x = 0; x < xcds; ++x)
+        if (tab.qmap[x] < 0 || tab.qmap[x] >= nq) return fail("an XCD without a queue");
+
+    // 2. tile footprints against the buffers of the item that owns the task
+    auto owner = [&](const void* p) -> int {
+        for (int i = 0; i < n; ++i) {
+            const ItemBufs& b = bufs[(size_t)i];
+            for (const Buf* x : {&b.in, &b.mid, &b.out, &b.work})
+                if (x->base && (uintptr_t)p >= x->base && (uintptr_t)p < x->base + x->bytes) return i;
+        }
+        return -1;
+    };
+    auto ok_range = [&](int item, uintptr_t lo, size_t len) {
+        const ItemBufs& b = bufs[(size_t)item];
+        return inside(lo, len, b.in) || inside(lo, len, b.mid) || inside(lo, len, b.out) || inside(lo, len, b.work);
+    };
+    for (int k = 0; k < nt; ++k) {
+        const BatchTask& t = tab.tasks[(size_t)k];
+        const int item = owner(t.in);
+        if (item < 0 || owner(t.out) != item) return fail("task buffers belong to no item / two items");
+        const Plan& p = plans[(size_t)item];
+        const int es = 2 * p.elem;  // complex element
+        for (int tile = 0; tile < t.ntiles; ++tile) {
+            uintptr_t lo;
+            size_t len;
+            bool good = true;
+            switch (t.kind) {
+            case kBkPlaneR2C:
+            case kBkPlaneC2R: {
+                const int64_t p0 = (int64_t)tile * t.a0;
+                const int64_t np = std::min<int64_t>(t.a0, t.i0 - p0);
+                if (np < 1) return fail("plane tile past the end");
+                const int64_t rin = t.kind == kBkPlaneR2C ? p.n1 * p.h : p.n1 * p.H;
+                const int64_t rout = t.kind == kBkPlaneR2C ? p.n1 * p.H : p.n1 * p.h;
+                span(t.in, p0 * rin, np * rin, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                span(t.out, p0 * rout, np * rout, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                if (np * p.n1 * p.H > (int64_t)kNtSmall * (p.elem == 8 ? 8 : 16)) return fail("plane tile too big");
+                break;
+            }
+            case kBkRowsR2C:
+            case kBkRowsC2R: {
+                const int64_t r0 = (int64_t)tile * t.a0;
+                const int64_t rows = std::min<int64_t>(t.a0, t.i0 - r0);
+                if (rows < 1) return fail("rows tile past the end");
+                const int64_t win = t.kind == kBkRowsR2C ? p.h : p.H, wout = t.kind == kBkRowsR2C ? p.H : p.h;
+                span(t.in, r0 * win, rows * win, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                span(t.out, r0 * wout, rows * wout, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                if (rows * p.h > (int64_t)kNtSmall * (p.elem == 8 ? 8 : 16)) return fail("rows tile too big");
+                if ((int64_t)rows * p.Hs * es > (int64_t)tab.lds) return fail("rows tile over its LDS");
+                break;
+            }
+            default: {
+                const int W = t.a0;
+                const int b = tile / t.a1;
+                const int64_t c0 = (int64_t)(tile - b * t.a1) * W;
+                const int64_t width = std::min<int64_t>(W, t.i1 - c0);
+                if (width < 1) return fail("column tile past the end");
+                const int64_t nrows = (t.s0 == p.d_sched) ? p.n0 : p.n1;
+                const int64_t off = (int64_t)b * t.i2 + c0;
+                span(t.in, off, (nrows - 1) * t.i0 + width, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                span(t.out, off, (nrows - 1) * t.i0 + width, es, lo, len);
+                good = good && ok_range(item, lo, len);
+                if (nrows * W > (int64_t)kNtSmall * (p.elem == 8 ? 8 : 16)) return fail("column tile too big");
+                break;
+            }
+            }
+            if (!good) return fail("task " + std::to_string(k) + " tile " + std::to_string(tile) + " outside its buffers");
+        }
+    }
+
+    // 3. the ticket protocol on G threads
+    std::vector<std::atomic<int>> ticket((size_t)nq);
+    std::atomic<int> exited{0}, err{0};
+    std::vector<std::atomic<int>> done((size_t)nt);
+    std::vector<std::vector<std::atomic<int>>> runs((size_t)nq);
+    for (auto& t : ticket) t.store(0);
+    for (auto& d : done) d.store(0);
+    for (int q = 0; q < nq; ++q) {
+        std::vector<std::atomic<int>> v((size_t)tab.queue_tickets[(size_t)q]);
+        for (auto& r : v) r.store(0);
+        runs[(size_t)q].swap(v);
+    }
+    std::vector<int> item_xcd((size_t)n, -1);  // XCD that ran the item's first tile (pinned check)
+    std::vector<int> task_item((size_t)nt, -1);
+    for (int k = 0; k < nt; ++k) task_item[(size_t)k] = owner(tab.tasks[(size_t)k].in);
+    std::mutex mu;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto wg = [&](int g) {
+        const int xcc = g % xcds;
+        const int q = tab.qmap[xcc];
+        const int tb = tab.task_begin[(size_t)q], nqk = tab.task_begin[(size_t)q + 1] - tb;
+        const int32_t* firsts = tab.firsts.data() + tb + q;
+        const int total = firsts[nqk];
+        int nxt = ticket[(size_t)q].fetch_add(1), cur = 0, checked = -1;
+        for (;;) {
+            const int t = nxt;
+            if (t >= total) break;
+            nxt = ticket[(size_t)q].fetch_add(1);
+            if (firsts[cur + 1] <= t) {
+                int lo = cur + 1, step = 1;
+                while (lo + step < nqk && firsts[lo + step] <= t) {
+                    lo += step;
+                    step *= 2;
+                }
+                int hi = lo + step < nqk ? lo + step : nqk;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (firsts[mid] <= t) lo = mid;
+                    else hi = mid;
+                }
+                cur = lo;
+            }
+            if (!(firsts[cur] <= t && t < firsts[cur + 1])) {
+                err.store(1);
+                break;
+            }
+            const int k = tb + cur;
+            const BatchTask& tk = tab.tasks[(size_t)k];
+            if (k != checked) {
+                checked = k;
+                if (tk.dep >= 0) {
+                    while (done[(size_t)tk.dep].load() < tk.dep_tiles) {
+                        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) {
+                            err.store(2);
+                            exited.fetch_add(1);
+                            return;
+                        }
+                        std::this_thread::yield();
+                    }
+                }
+            }
+            if (tk.dep >= 0 && done[(size_t)tk.dep].load() != tk.dep_tiles) err.store(3);
+            if (tab.pinned) {
+                std::lock_guard<std::mutex> lk(mu);
+                int& x = item_xcd[(size_t)task_item[(size_t)k]];
+                if (x < 0) x = xcc;
+                else if (x != xcc) err.store(4);
+            }
+            runs[(size_t)q][(size_t)t].fetch_add(1);
+            done[(size_t)k].fetch_add(1);
+        }
+        exited.fetch_add(1);
+    };
+    std::vector<std::thread> th;
+    for (int g = 0; g < G; ++g) th.emplace_back(wg, g);
+    for (auto& x : th) x.join();
+    if (err.load()) return fail("protocol error " + std::to_string(err.load()));
+    if (exited.load() != G) return fail("a workgroup did not leave");
+    for (int q = 0; q < nq; ++q)
+        for (size_t t = 0; t < runs[(size_t)q].size(); ++t)
+            if (runs[(size_t)q][t].load() != 1)
+                return fail("queue " + std::to_string(q) + " ticket " + std::to_string(t) + " ran " +
+                            std::to_string(runs[(size_t)q][t].load()) + " times");
+    for (int k = 0; k < nt; ++k)
+        if (done[(size_t)k].load() != tab.tasks[(size_t)k].ntiles) return fail("task not complete");
+    printf("ok %d %lld %zu %d\n", nt, (long long)tab.tickets, tab.lds, tab.pinned ? 1 : 0);
+    return 0;
+}

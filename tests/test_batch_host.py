@@ -1,0 +1,110 @@
+"""CPU tests of the batched launch's host side: the task lists that
+build_batch_table produces, and the ticket protocol the batched kernel runs,
+exercised by tests/batch_sim.cpp (the library's own host code, fake device
+addresses, the scheduling loop on host threads)."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1406_5597_amd import fields
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sim(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("sim") / "batch_sim")
+    csrc = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
+    cmd = ["g++", "-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           os.path.join(ROOT, "tests", "batch_sim.cpp"), os.path.join(csrc, "fft3d_plan.cpp"),
+           os.path.join(csrc, "fft3d_batch_host.cpp"), "-L/opt/rocm/lib", "-lamdhip64", "-lpthread",
+           "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail("batch_sim build failed:\n" + r.stderr[-3000:])
+
+    def run(lines, workgroups=64, lag=None, mode=None, xcds=None):
+        head = ""
+        if lag is not None:
+            head += "lag %d\n" % lag
+        if mode is not None:
+            head += "mode %d\n" % mode
+        if xcds is not None:
+            head += "xcds %d\n" % xcds
+        p = subprocess.run([exe, str(workgroups)], input=head + "\n".join(lines) + "\n", capture_output=True,
+                           text=True, timeout=120)
+        out = p.stdout.strip()
+        assert p.returncode == 0 and out.startswith("ok"), out + p.stderr
+        _, tasks, tickets, lds, pinned = out.split()
+        return int(tasks), int(tickets), int(lds), bool(int(pinned))
+    return run
+
+
+def item(shape, dtype, direction, work=1):
+    return "%d %d %d %d %d %d" % (shape[0], shape[1], shape[2], 1 if dtype == "f64" else 0, direction, work)
+
+
+def test_mixed_batch_tables_and_protocol(sim):
+    """The 64-field mix: 4 passes per field (2 for fields whose plane step is
+    split in the batch: rows + n1 columns each way), every tile inside its
+    buffers, the protocol completes on 256 workgroups."""
+    mix = fields.batch_mix(64, seed=4)
+    tasks, tickets, lds, pinned = sim([item(s, d, 2) for s, d in mix], workgroups=256)
+    assert tasks >= 4 * 64 and tickets > 0
+    assert lds <= 80 * 1024 - 256
+    assert pinned, "64 mixed fields balance over 8 XCDs"
+    # the same as one queue
+    sim([item(s, d, 2) for s, d in mix], workgroups=256, mode=2)
+
+
+@pytest.mark.parametrize("lag", [1, 2, 3, 7, 1000])
+def test_ticket_orders(sim, lag):
+    mix = fields.batch_mix(24, seed=11)
+    sim([item(s, d, 2) for s, d in mix], workgroups=32, lag=lag)
+
+
+def test_every_direction_and_big_shapes(sim):
+    """Directions with and without work, degenerate axes, and shapes whose own
+    kernels are big-tier (retiled to the small tier in a batch)."""
+    shapes = [(1, 1, 2), (2, 3, 4), (1, 8, 16), (8, 1, 8), (12, 9, 24), (96, 96, 96), (128, 128, 128),
+              (192, 192, 96), (256, 256, 256), (8, 512, 512), (3, 1024, 1024), (1024, 2, 2), (2, 2048, 16),
+              (4, 16, 4096), (729, 4, 6), (512, 512, 512), (4096, 4, 4)]
+    lines = []
+    for i, s in enumerate(shapes):
+        for d in ("f32", "f64"):
+            lines.append(item(s, d, i % 3, work=(i // 3) % 2))
+    sim(lines, workgroups=96)
+
+
+def test_random_mixes(sim):
+    rng = np.random.default_rng(5)
+    ext = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128]
+    for trial in range(6):
+        lines = []
+        for _ in range(int(rng.integers(1, 40))):
+            n0, n1 = (int(rng.choice(ext)) for _ in range(2))
+            n2 = 2 * int(rng.choice(ext))
+            lines.append(item((n0, n1, n2), ("f32", "f64")[int(rng.integers(2))], int(rng.integers(3)),
+                              int(rng.integers(2))))
+        sim(lines, workgroups=int(rng.integers(1, 200)), lag=int(rng.integers(0, 5)) or None)
+
+
+def test_one_workgroup_drains_everything(sim):
+    """A single workgroup per queue still finishes (every wait is for a
+    smaller ticket of the same queue)."""
+    three = [item((32, 32, 32), "f32", 2), item((16, 8, 12), "f64", 2), item((8, 8, 8), "f32", 0)]
+    sim(three, workgroups=1, mode=2)
+    sim(three, workgroups=8, mode=1)
+
+
+def test_pinning_choice(sim):
+    """Auto mode pins items to XCDs only when that balances them: one big
+    item among small ones stays on one queue; queue counts follow the XCDs."""
+    lop = [item((192, 192, 96), "f64", 2)] + [item((32, 32, 32), "f32", 2)] * 3
+    assert not sim(lop, workgroups=64)[3]
+    even = [item((64, 64, 64), "f32", 2)] * 16
+    assert sim(even, workgroups=64)[3]
+    assert sim(even, workgroups=12, xcds=4, mode=1)[3]
+    assert not sim(even, workgroups=12, xcds=1)[3]

@@ -188,21 +188,29 @@ def test_batch_retiles_big_items_bit_identically(F):
         it.check_bits()
 
 
-@pytest.mark.parametrize("lag", ["1", "2", "5"])
-def test_ticket_orders_give_same_bits(F, lag):
+@pytest.mark.parametrize("mode", ["pinned", "spread"])
+@pytest.mark.parametrize("lag", ["0", "1", "2", "5"])
+def test_ticket_orders_give_same_bits(F, lag, mode):
     """Other ticket orders (an item's passes `lag` slots apart instead of
-    pass-major) change only the schedule, never the bits."""
+    pass-major) and both queue modes (items pinned to XCDs, or one queue for
+    all) change only the schedule, never the bits."""
     mix = fields.batch_mix(12, seed=7)
-    say("batch: lag %s" % lag)
+    say("batch: lag %s mode %s" % (lag, mode))
     items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 5000 + i) for i, (s, d) in enumerate(mix)]
     os.environ["FFT3D_BATCH_LAG"] = lag
+    os.environ["FFT3D_BATCH_MODE"] = mode
     try:
+        b = F.Batch([it.tuple() for it in items])
+        assert b.describe()["mode"] == mode
+        b.launch()
         F.fft3d_batch_submit([it.tuple() for it in items])
     finally:
         del os.environ["FFT3D_BATCH_LAG"]
+        del os.environ["FFT3D_BATCH_MODE"]
     _sync()
     for it in items:
         it.check_bits()
+    assert b.status() == 0
 
 
 def test_sequential_flag_matches(F):
