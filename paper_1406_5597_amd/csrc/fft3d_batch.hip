@@ -132,7 +132,15 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(const void* __restrict__ ima
         firsts = reinterpret_cast<const int*>(&hd + 1) + tb + q;  // nq + 1 entries
         ticket = ctr + kBatchCtrQueueStride * q;
     }
-    const int total = q >= 0 ? firsts[nq] : 0;
+    // the queue's ticket table in LDS when it fits (thread 0 searches it for
+    // every ticket)
+    __shared__ int s_firsts[kBatchFirstsCache];
+    const bool cached = q >= 0 && nq + 1 <= kBatchFirstsCache;
+    if (cached)
+        for (int i = (int)threadIdx.x; i <= nq; i += kNtSmall) s_firsts[i] = firsts[i];
+    __syncthreads();
+    auto first_of = [&](int i) { return cached ? s_firsts[i] : firsts[i]; };
+    const int total = q >= 0 ? first_of(nq) : 0;
     // thread 0's scheduling state
     int next = 0, cur = 0, checked = -1, failed = -1;
     if (threadIdx.x == 0 && q >= 0) next = atomicAdd(ticket, 1);
@@ -143,22 +151,22 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(const void* __restrict__ ima
             if (t < total) {
                 next = atomicAdd(ticket, 1);  // the next ticket, while this one runs
                 // task of ticket t: firsts[cur] <= t (tickets only grow)
-                if (firsts[cur + 1] <= t) {
+                if (first_of(cur + 1) <= t) {
                     int lo = cur + 1, step = 1;
-                    while (lo + step < nq && firsts[lo + step] <= t) {
+                    while (lo + step < nq && first_of(lo + step) <= t) {
                         lo += step;
                         step *= 2;
                     }
                     int hi = lo + step < nq ? lo + step : nq;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
-                        if (firsts[mid] <= t) lo = mid;
+                        if (first_of(mid) <= t) lo = mid;
                         else hi = mid;
                     }
                     cur = lo;
                 }
                 k = tb + cur;
-                tile = t - firsts[cur];
+                tile = t - first_of(cur);
                 if (k != checked) {
                     checked = k;
                     const int dep = tasks[k].dep;

@@ -59,6 +59,9 @@ struct BatchTask {
 // tiles, so a pass's output is read back through the same L2 it was written
 // to) or a single queue that every workgroup serves ("spread").
 constexpr int kBatchMaxQueues = 16;
+// A queue's ticket table is copied to LDS when it has at most this many
+// entries (tasks + 1).
+constexpr int kBatchFirstsCache = 512;
 
 // Head of the device image of a batch, followed by the per-queue ticket
 // tables (queue q: the first ticket of each of its tasks, then its total) and

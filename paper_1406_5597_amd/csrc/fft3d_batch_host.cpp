@@ -51,16 +51,48 @@ struct ItemTiling {
     ColPass pass0;
 };
 
+int small_tier_elems(const Plan& p)
+{
+    return kNtSmall * (p.dtype == FFT3D_F64 ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
+}
+
+// Widest column tile of the small tier: W doubles while the tile (n rows by
+// W columns) fits the tier and the batch's LDS budget and W does not pass the
+// block's column count.  Small fields get fewer, larger tiles this way.
+void widen_cols(ColPass& cp, int64_t n, const Plan& p)
+{
+    const int64_t es = small_tier_elems(p), cxs = 2 * p.elem;
+    while ((int64_t)cp.W * 2 <= cp.ncols && n * cp.W * 2 <= es && n * cp.W * 2 * cxs <= kBatchLdsCap) cp.W *= 2;
+    cp.wshift = 0;
+    while ((1 << cp.wshift) < cp.W) ++cp.wshift;
+    cp.tiles_per_batch = (cp.ncols + cp.W - 1) / cp.W;
+    cp.lds = (size_t)(n * cp.W * cxs);
+}
+
+bool batch_widen()
+{
+    const char* v = getenv("FFT3D_BATCH_WIDEN");
+    return !v || atoi(v) != 0;
+}
+
 const char* item_tiling(const Plan& p, ItemTiling& t)
 {
+    const bool widen = batch_widen();
     if (p.n0 > 1) {
         t.pass0 = p.pass0;
         if (t.pass0.big && !small_colpass(p, 0, t.pass0)) return "n0 too long for a small-tier column tile";
+        if (widen) widen_cols(t.pass0, p.n0, p);
     }
     if (p.fused_plane && !p.plane_big && p.plane_lds <= kBatchLdsCap) {
         t.fused = true;
         t.plane_lds = p.plane_lds;
         t.ppw = p.ppw;
+        if (widen) {
+            // several small planes per tile, within the tier and the LDS budget
+            const int64_t es = small_tier_elems(p), pe = p.n1 * p.H;
+            while (t.ppw * 2 <= p.n0 && (t.ppw * 2) * pe <= es && (size_t)(t.ppw * 2) * p.plane_lds <= kBatchLdsCap)
+                t.ppw *= 2;
+        }
         return nullptr;
     }
     bool rows_big = false;
@@ -83,6 +115,7 @@ const char* item_tiling(const Plan& p, ItemTiling& t)
         t.rows_lds = (size_t)(t.rpw * row_bytes);
     }
     if (p.n1 > 1 && t.pass1.big && !small_colpass(p, 1, t.pass1)) return "n1 too long for a small-tier column tile";
+    if (p.n1 > 1 && widen) widen_cols(t.pass1, p.n1, p);
     return nullptr;
 }
 

@@ -45,9 +45,9 @@ struct BatchTable {
 };
 
 constexpr int kBatchSpinLimit = 1 << 20;
-// LDS of one batch tile: half a CU's LDS less the kernel's own few words, so
-// that two workgroups fit on a CU.
-constexpr int64_t kBatchLdsCap = kLdsHalf - 256;
+// LDS of one batch tile: half a CU's LDS less the kernel's own (scheduling
+// words and the cached ticket table), so that two workgroups fit on a CU.
+constexpr int64_t kBatchLdsCap = kLdsHalf - 2560;
 constexpr int kRingSlots = 8;     // task images fft3d_batch_submit may have in flight per device
 constexpr int kRingTasks = 4096;  // tasks per ring slot
 
