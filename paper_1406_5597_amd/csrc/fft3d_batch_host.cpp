@@ -200,6 +200,17 @@ void chain_c2r(std::vector<BatchTask>& chain, const Plan& p, const ItemTiling& p
     }
 }
 
+// Rough time of a task on one workgroup, for placing items on XCDs: per tile
+// a fixed part (scheduling, load latency, store drain; about 4 us measured on
+// MI355X) plus its LDS-sized data at about 16 GB/s per CU; the plane tiles do
+// two axes and the split of the real transform, about 1.6x the work.
+int64_t task_cost_ns(const BatchTask& t)
+{
+    int64_t tile = 4000 + t.lds / 16;
+    if (t.kind == kBkPlaneR2C || t.kind == kBkPlaneC2R) tile = tile * 8 / 5;
+    return (int64_t)t.ntiles * tile;
+}
+
 }  // namespace
 
 const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions& o, BatchTable& tab)
@@ -225,7 +236,7 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
         }
         for (const BatchTask& t : c) {
             lds = std::max(lds, (size_t)t.lds);
-            load[(size_t)i] += (int64_t)t.ntiles * t.lds;  // about the bytes the task moves
+            load[(size_t)i] += task_cost_ns(t);
         }
     }
 
