@@ -206,6 +206,115 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     }
 
 
+def served_bytes_alg(shape, dtype, direction, ncomp=3) -> int:
+    """Algorithmic bytes of one request: the passes of one direction (half a
+    pair), per field."""
+    return ncomp * pair_bytes_alg(shape, 4 if dtype == "f32" else 8) // 2
+
+
+def run_served(F, torch, fields, rate=200.0, measured=2000, warmup_s=5.0, seed=5, budget=200 * 10**9,
+               nstreams=4, log=None):
+    """The served stream: Poisson arrivals of mean `rate`/s of 3-component
+    velocity-field requests (fields.serve_mix: shapes 64^3 .. 512^3, 2% 1024^3
+    FP32, 80/20 FP32/FP64, r2c or c2r), admitted under an HBM budget, run by
+    the library's server (continuous batching on `nstreams` streams).  Inputs
+    are resident pools, one 3-component field and one 3-component spectrum
+    per (shape, dtype) (fields.velocity_pool_torch).  The first warmup_s
+    seconds of arrivals are not measured; then `measured` requests.
+    Latency = done - arrival (server clock)."""
+    import threading
+    import numpy as np
+
+    n_warm = int(rate * warmup_s)
+    count = n_warm + measured
+    arrive, reqs = fields.serve_mix(count, rate, seed)
+    keys = sorted({(s, d) for s, d, _ in reqs})
+    pools = {}
+    t0 = time.time()
+    for i, (s, d) in enumerate(keys):
+        u, U = fields.velocity_pool_torch(s, 2000 + i, d)
+        pools[(s, d)] = ([u[c] for c in range(3)], [U[c] for c in range(3)])
+        torch.cuda.synchronize()
+    if log:
+        log("# served pools: %d (shape, dtype) in %.1f s" % (len(keys), time.time() - t0))
+    torch.cuda.empty_cache()
+    srv = None
+    while srv is None:
+        try:
+            srv = F.Server(budget, nstreams=nstreams)
+        except F.Fft3dError:
+            if budget <= 16 * 10**9:
+                raise
+            budget = budget * 3 // 4  # what the device has left after the pools
+    if log:
+        log("# served budget %.1f GB" % (budget / 1e9))
+    # plans and first launches outside the measurement
+    for s, d in keys:
+        for r in (0, 1):
+            rid = srv.submit(s, d, r, pools[(s, d)][r])
+            srv.wait(rid, 120.0)
+            srv.release(rid)
+    ids = [None] * count
+    done = [None] * count
+    errors = []
+
+    def producer():
+        start = time.perf_counter()
+        for i in range(count):
+            dt = start + arrive[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            s, d, r = reqs[i]
+            ids[i] = srv.submit(s, d, r, pools[(s, d)][r])
+
+    def consumer():
+        try:
+            for i in range(count):
+                while ids[i] is None:
+                    time.sleep(5e-5)
+                srv.wait(ids[i], 300.0)
+                _, t = srv.result(ids[i], 3)
+                done[i] = t
+                srv.release(ids[i])
+        except Exception as e:
+            errors.append(e)
+
+    tp = threading.Thread(target=producer)
+    tc = threading.Thread(target=consumer)
+    tp.start()
+    tc.start()
+    tp.join()
+    tc.join()
+    st = srv.stats()
+    srv.close()
+    if errors:
+        raise errors[0]
+    meas = list(range(n_warm, count))
+    lat = np.array([done[i][3] - done[i][0] for i in meas])
+    qwait = np.array([done[i][1] - done[i][0] for i in meas])
+    span = done[meas[-1]][3] - done[meas[0]][0]
+    nbytes = sum(served_bytes_alg(*reqs[i]) for i in meas)
+    del pools
+    torch.cuda.empty_cache()
+    return {
+        "workload": "Poisson arrivals at %.0f/s of 3-component k^-5/3 velocity-field requests: shapes %s, "
+                    "plus %s FP32 with probability 0.02; 80/20 FP32/FP64; r2c or c2r 50/50; budget %.0f GB; "
+                    "%d warm-up + %d measured requests (seed %d)" % (
+                        rate, "/".join("x".join(map(str, s)) for s in fields.SERVE_SHAPES),
+                        "x".join(map(str, fields.SERVE_LARGE)), budget / 1e9, n_warm, measured, seed),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "mean_ms": round(float(lat.mean()) * 1e3, 3),
+        "p99_queue_ms": round(float(np.percentile(qwait, 99)) * 1e3, 3),
+        "completed_req_s": round(len(meas) / span, 1),
+        "GB_s_alg": round(nbytes / span / 1e9, 1),
+        "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 3),
+        "budget_GB": round(st["budget_bytes"] / 1e9, 3),
+        "batched_launches": st["batched_launches"],
+        "single_launches": st["single_launches"],
+    }
+
+
 def kernel_source_sha256() -> str:
     """Hash of the HIP/C++ sources of the library: a traffic figure measured on
     other sources is stale."""
@@ -259,6 +368,10 @@ def main() -> int:
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s) of the served stream")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per served rate")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="seconds of unmeasured arrivals first")
     ap.add_argument("--coop-plane", action="store_true",
                     help="cooperative one-launch plane step for large planes instead of the two kernels")
     args = ap.parse_args()
@@ -295,6 +408,18 @@ def main() -> int:
         print("# batch: %.3f ms/launch (%.1f fields/s, %.1f GB/s), per-field launches %.3f ms" % (
             batch["ms_per_launch"], batch["fields_s"], batch["GB_s_alg"], batch["ms_per_field_launches"]),
             file=sys.stderr, flush=True)
+
+    served = None
+    if not args.no_serve:
+        served = []
+        for rate in [float(v) for v in args.serve_rates.split(",") if v]:
+            print("# served stream at %.0f req/s ..." % rate, file=sys.stderr, flush=True)
+            sv = run_served(F, torch, fields, rate=rate, measured=args.serve_requests, warmup_s=args.serve_warmup,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+            print("# served: p50 %.3f ms, p99 %.3f ms, %.1f req/s" % (sv["p50_ms"], sv["p99_ms"],
+                                                                       sv["completed_req_s"]),
+                  file=sys.stderr, flush=True)
+            served.append(sv)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -355,6 +480,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "copy_GB_s": round(copy_gbs, 1),
         "batch": batch,
+        "served": served,
     }
     for k in ("rel_l2_r2c", "rel_l2_c2r"):
         if k in r:

@@ -244,6 +244,76 @@ int64_t fft3d_plan_twiddles(fft3d_plan_t p, int which, double* out, int64_t coun
  * Requires p >= 1, n0 % p == 0, ncols % p == 0, 0 <= src, dst < p. */
 int fft3d_exchange_block(int64_t n0, int64_t ncols, int64_t p, int64_t src, int64_t dst, int64_t* out);
 
+/* ---- Serving: continuous batching of transform requests ----------------
+ *
+ * A server owns a device arena of `budget_bytes` (allocated once, at
+ * creation) from which it places every request's outputs and work buffers,
+ * a cache of plans, a dispatcher thread and `nstreams` streams.  A request --
+ * r2c or c2r of `ncomp` fields of one shape and dtype (say the three
+ * components of a velocity field) -- is admitted when its bytes fit in what
+ * the arena has free (first come, first served: a request waits behind an
+ * earlier one that does not fit yet), then launched at once on the next
+ * stream: requests of at most `batch_points` real points per field go, with
+ * every other such request admitted in the same round, through one batched
+ * launch (fft3d_batch_submit), larger ones through fft3d_r2c / fft3d_c2r per
+ * field.  Requests that arrive while others run are admitted and launched as
+ * memory frees up, so their work overlaps on the device.  Every result is
+ * bit-identical to the same transform run alone.  A request's outputs stay in
+ * the arena until fft3d_server_release; its work buffers are freed when it
+ * completes.  Inputs are the caller's (device, not modified, valid until the
+ * request completes). */
+typedef struct fft3d_server_s* fft3d_server_t;
+
+enum { FFT3D_SERVER_NO_DEVICE = 1 }; /* host logic only: the arena is address
+                                        arithmetic, plans are host-only, no
+                                        kernel runs and a request completes as
+                                        soon as it is launched (for tests) */
+
+typedef struct {
+    size_t budget_bytes;  /* arena size (outputs + work buffers of admitted requests) */
+    int nstreams;         /* 1..16 streams (0: 4) */
+    int64_t batch_points; /* per-field size limit of batched requests (0: 2^21 real points) */
+    int max_batch_items;  /* fields per batched launch (0: 192) */
+    int flags;            /* FFT3D_SERVER_* */
+} fft3d_server_config;
+
+#define FFT3D_SERVER_MAX_COMP 8
+
+typedef struct {
+    int64_t n0, n1, n2;
+    int dtype; /* FFT3D_F32 / FFT3D_F64 */
+    int dir;   /* FFT3D_R2C (in: real fields, out: spectra) or FFT3D_C2R (in: spectra, out: real fields) */
+    int ncomp; /* 1..FFT3D_SERVER_MAX_COMP fields */
+    const void* in[FFT3D_SERVER_MAX_COMP];
+} fft3d_request;
+
+typedef struct {
+    int64_t submitted, admitted, completed, released, waiting, in_flight;
+    int64_t batched_launches, single_launches;
+    size_t reserved_bytes, peak_reserved_bytes, budget_bytes;
+} fft3d_server_counters;
+
+/* Create a server on the current device (allocates the arena, streams and the
+ * dispatcher thread).  FFT3D_ERR_NOMEM if the arena cannot be allocated. */
+int fft3d_server_create(const fft3d_server_config* cfg, fft3d_server_t* out);
+/* Queue a request (thread-safe, returns at once; its arrival time is now).
+ * *id receives the request's id.  FFT3D_ERR_BUDGET if the request alone needs
+ * more than the whole budget; FFT3D_ERR_UNSUPPORTED for a shape no plan can
+ * take. */
+int fft3d_server_submit(fft3d_server_t s, const fft3d_request* r, int64_t* id);
+/* Wait until the request has completed: 1 done, 0 timed out (timeout_s < 0:
+ * no limit), negative on error (unknown id, a failed launch). */
+int fft3d_server_wait(fft3d_server_t s, int64_t id, double timeout_s);
+/* Outputs of a completed request (out: ncomp device pointers into the arena)
+ * and its times in seconds on the server's clock (times: arrive, admit,
+ * launch, done).  Either may be NULL.  FFT3D_ERR_INVALID_ARG until done. */
+int fft3d_server_result(fft3d_server_t s, int64_t id, void** out, double* times);
+/* Free a completed request's outputs (waiting requests may then be admitted). */
+int fft3d_server_release(fft3d_server_t s, int64_t id);
+int fft3d_server_stats(fft3d_server_t s, fft3d_server_counters* st);
+/* Stop accepting, finish what was admitted, free everything. */
+int fft3d_server_destroy(fft3d_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -330,6 +330,10 @@ fft3d::BatchOptions batch_options(int device)
 
 }  // namespace
 
+namespace fft3d {
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace fft3d
+
 extern "C" {
 
 int fft3d_version(void) { return 100; }

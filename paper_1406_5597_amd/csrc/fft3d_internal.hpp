@@ -150,6 +150,8 @@ hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows,
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t stream);
 hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inverse, hipStream_t stream);
+// The message fft3d_last_error() returns on this thread.
+void set_last_error(const std::string& m);
 // Raise the dynamic-LDS limit of every kernel once per process.
 hipError_t kernels_init();
 // Device part of the cooperative plane step: grid from occupancy on the

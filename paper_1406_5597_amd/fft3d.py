@@ -37,6 +37,8 @@ FFT3D_PASS_N1_INV = 4
 FFT3D_PASS_PLANE_C2R = 5
 FFT3D_BATCH_SEQUENTIAL = 2
 FFT3D_BATCH_DIRECT = 4
+FFT3D_SERVER_NO_DEVICE = 1
+FFT3D_SERVER_MAX_COMP = 8
 
 # Every symbol include/fft3d.h declares.
 EXPORTS = (
@@ -45,6 +47,8 @@ EXPORTS = (
     "fft3d_strerror", "fft3d_last_error", "fft3d_plan_describe", "fft3d_plan_twiddles",
     "fft3d_exchange_block", "fft3d_run_pass", "fft3d_batch_submit_ex", "fft3d_batch_create",
     "fft3d_batch_launch", "fft3d_batch_status", "fft3d_batch_describe", "fft3d_batch_destroy",
+    "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
+    "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy",
 )
 
 
@@ -57,6 +61,22 @@ class Fft3dError(RuntimeError):
 class BatchItem(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("dir", ctypes.c_int), ("in_", ctypes.c_void_p),
                 ("mid", ctypes.c_void_p), ("out", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("nstreams", ctypes.c_int), ("batch_points", ctypes.c_int64),
+                ("max_batch_items", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("dtype", ctypes.c_int),
+                ("dir", ctypes.c_int), ("ncomp", ctypes.c_int), ("in_", ctypes.c_void_p * FFT3D_SERVER_MAX_COMP)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "admitted", "completed", "released", "waiting",
+                                              "in_flight", "batched_launches", "single_launches")] + \
+               [(n, ctypes.c_size_t) for n in ("reserved_bytes", "peak_reserved_bytes", "budget_bytes")]
 
 
 def _load() -> ctypes.CDLL:
@@ -89,6 +109,13 @@ def _load() -> ctypes.CDLL:
         "fft3d_batch_status": (ctypes.c_int, [vp]),
         "fft3d_batch_describe": (ctypes.c_int, [vp, ctypes.c_char_p, sz]),
         "fft3d_batch_destroy": (ctypes.c_int, [vp]),
+        "fft3d_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+        "fft3d_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "fft3d_server_wait": (ctypes.c_int, [vp, i64, ctypes.c_double]),
+        "fft3d_server_result": (ctypes.c_int, [vp, i64, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double)]),
+        "fft3d_server_release": (ctypes.c_int, [vp, i64]),
+        "fft3d_server_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerCounters)]),
+        "fft3d_server_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -316,6 +343,112 @@ def fft3d_exchange_block(n0: int, ncols: int, p: int, src: int, dst: int):
     _check(lib.fft3d_exchange_block(n0, ncols, p, src, dst, out))
     v = list(out)
     return tuple(v[:4]), tuple(v[4:])
+
+
+class Server:
+    """A serving loop on the current device (see include/fft3d.h, "Serving"):
+    submit r2c / c2r requests of 1..8 fields, wait, read the outputs (device
+    addresses in the server's arena) and times, release."""
+
+    def __init__(self, budget_bytes: int, nstreams: int = 0, batch_points: int = 0, max_batch_items: int = 0,
+                 flags: int = 0):
+        cfg = ServerConfig(int(budget_bytes), int(nstreams), int(batch_points), int(max_batch_items), int(flags))
+        h = ctypes.c_void_p()
+        _check(lib.fft3d_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h.value
+
+    def submit(self, shape, dtype: str, direction: int, inputs) -> int:
+        r = Request()
+        r.n0, r.n1, r.n2 = (int(v) for v in shape)
+        r.dtype = FFT3D_F32 if dtype == "f32" else FFT3D_F64
+        r.dir = int(direction)
+        r.ncomp = len(inputs)
+        for i, a in enumerate(inputs):
+            r.in_[i] = _addr(a)
+        rid = ctypes.c_int64()
+        _check(lib.fft3d_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = -1.0) -> bool:
+        return _check(lib.fft3d_server_wait(self.handle, int(rid), float(timeout))) == 1
+
+    def result(self, rid: int, ncomp: int):
+        """(output device addresses, (t_arrive, t_admit, t_launch, t_done))."""
+        out = (ctypes.c_void_p * ncomp)()
+        times = (ctypes.c_double * 4)()
+        _check(lib.fft3d_server_result(self.handle, int(rid), out, times))
+        return [o for o in out], tuple(times)
+
+    def release(self, rid: int) -> None:
+        _check(lib.fft3d_server_release(self.handle, int(rid)))
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib.fft3d_server_stats(self.handle, ctypes.byref(c)))
+        return {n: getattr(c, n) for n, _ in ServerCounters._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.fft3d_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def fft3d_server_create(budget_bytes: int, **kw) -> Server:
+    return Server(budget_bytes, **kw)
+
+
+def fft3d_server_submit(server: Server, shape, dtype: str, direction: int, inputs) -> int:
+    return server.submit(shape, dtype, direction, inputs)
+
+
+def fft3d_server_wait(server: Server, rid: int, timeout: float = -1.0) -> bool:
+    return server.wait(rid, timeout)
+
+
+def fft3d_server_result(server: Server, rid: int, ncomp: int):
+    return server.result(rid, ncomp)
+
+
+def fft3d_server_release(server: Server, rid: int) -> None:
+    server.release(rid)
+
+
+def fft3d_server_stats(server: Server) -> dict:
+    return server.stats()
+
+
+def fft3d_server_destroy(server: Server) -> None:
+    server.close()
+
+
+_HIP = None
+
+
+def copy_from_device(dst, src_addr: int, nbytes: int) -> None:
+    """Copy nbytes from a raw device address into the device tensor dst
+    (synchronous, for reading server outputs)."""
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.restype = ctypes.c_int
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    if nbytes > dst.numel() * dst.element_size():
+        raise ValueError("destination too small")
+    rc = _HIP.hipMemcpy(_addr(dst), int(src_addr), int(nbytes), 3)  # device to device
+    if rc != 0:
+        raise RuntimeError("hipMemcpy failed: %d" % rc)
 
 
 # ------------------------------------------------------------ conveniences --

@@ -30,6 +30,8 @@ fields:
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -181,3 +183,87 @@ def batch_mix(count: int = 64, seed: int = 4):
     si = rng.integers(0, len(BATCH_SHAPES), size=count)
     di = rng.integers(0, 2, size=count)
     return [(BATCH_SHAPES[int(a)], "f64" if int(b) else "f32") for a, b in zip(si, di)]
+
+
+SERVE_SHAPES = ((64, 64, 64), (128, 128, 128), (256, 256, 256), (256, 256, 128), (512, 512, 512))
+SERVE_LARGE = (1024, 1024, 1024)
+
+
+def serve_mix(count: int, rate: float, seed: int = 5, p_large: float = 0.02, p_f64: float = 0.2):
+    """The served stream: `count` requests with Poisson arrivals of mean rate
+    `rate` per second.  Each: shape uniform over SERVE_SHAPES, or SERVE_LARGE
+    (always FP32) with probability p_large; FP64 with probability p_f64
+    otherwise; r2c or c2r with probability 1/2; three components.  Returns
+    (arrival times in s from 0, list of (shape, dtype, direction) with
+    direction 0 = r2c, 1 = c2r)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    reqs = []
+    for _ in range(count):
+        if rng.random() < p_large:
+            shape, dt = SERVE_LARGE, "f32"
+        else:
+            shape = SERVE_SHAPES[int(rng.integers(len(SERVE_SHAPES)))]
+            dt = "f64" if rng.random() < p_f64 else "f32"
+        reqs.append((shape, dt, int(rng.integers(2))))
+    return t, reqs
+
+
+def velocity_pool_torch(shape, seed: int, dtype: str, device="cuda", kmax: int | None = None, slab: int = 32):
+    """GPU version of velocity_spectrum / velocity_field for the large fields of
+    the served workload (numpy takes minutes at 512^3 and more): the same
+    construction -- amplitude |k|^(-11/6) for 0 < |k| <= kmax, random phases
+    on the two unit vectors orthogonal to k -- with torch's seeded generator
+    (so not the same values as the numpy version), built in slabs of `slab`
+    k0 planes, synthesised with torch.fft.irfftn (rocFFT, a third-party
+    routine), all three components scaled so that mean(|u|^2)/3 = 1.  The
+    k2 = 0 and n2/2 planes are left as drawn (c2r reads them as defined for
+    any half spectrum).  Returns (real (3, n0, n1, n2), spectrum (3, n0, n1,
+    n2/2+1)) in the dtype ('f32' or 'f64'): the spectrum is the synthesised
+    one, scaled like the field, so that c2r of it is N times the field."""
+    import torch
+    n0, n1, n2 = shape
+    h = n2 // 2 + 1
+    if kmax is None:
+        kmax = default_kmax(shape)
+    rdt, cdt = (torch.float32, torch.complex64) if dtype == "f32" else (torch.float64, torch.complex128)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def signed(n):
+        i = torch.arange(n, device=device, dtype=rdt)
+        return torch.where(i < n / 2, i, i - n)
+
+    k1 = signed(n1).view(1, n1, 1)
+    k2 = torch.arange(h, device=device, dtype=rdt).view(1, 1, h)
+    U = torch.empty((3, n0, n1, h), dtype=cdt, device=device)
+    for a in range(0, n0, slab):
+        b = min(n0, a + slab)
+        k0 = signed(n0)[a:b].view(b - a, 1, 1)
+        K0, K1, K2 = torch.broadcast_tensors(k0, k1, k2)
+        kk = torch.sqrt(K0 * K0 + K1 * K1 + K2 * K2)
+        par = (K0 == 0) & (K1 == 0)
+        # e1 = k x a / |k x a|, a = z-hat (x-hat where k is parallel to z-hat)
+        az = torch.where(par, 0.0, 1.0).to(rdt)
+        ax = 1.0 - az
+        e1 = torch.stack((K1 * az, ax * K2 - K0 * az, -K1 * ax))
+        ne = torch.sqrt((e1 * e1).sum(0))
+        e1 = e1 / torch.where(ne > 0, ne, torch.ones_like(ne))
+        e2 = torch.stack((K1 * e1[2] - K2 * e1[1], K2 * e1[0] - K0 * e1[2], K0 * e1[1] - K1 * e1[0]))
+        e2 = e2 / torch.where(kk > 0, kk, torch.ones_like(kk))
+        amp = torch.where((kk > 0) & (kk <= kmax), kk.clamp(min=1.0) ** (-11.0 / 6.0), torch.zeros_like(kk))
+        p1 = torch.rand(kk.shape, generator=g, device=device, dtype=rdt) * (2 * math.pi)
+        p2 = torch.rand(kk.shape, generator=g, device=device, dtype=rdt) * (2 * math.pi)
+        w1 = torch.polar(amp / math.sqrt(2.0), p1)
+        w2 = torch.polar(amp / math.sqrt(2.0), p2)
+        U[:, a:b] = w1 * e1 + w2 * e2
+        del K0, K1, K2, kk, par, az, ax, e1, ne, e2, amp, p1, p2, w1, w2
+    u = torch.empty((3, n0, n1, n2), dtype=rdt, device=device)
+    for c in range(3):
+        u[c] = torch.fft.irfftn(U[c], s=(n0, n1, n2))
+    ms = float((u.double() ** 2).mean()) if u.numel() < (1 << 28) else float(
+        sum(float((u[c].double() ** 2).mean()) for c in range(3)) / 3)
+    scale = 1.0 / math.sqrt(ms) if ms > 0 else 1.0
+    u *= scale
+    U *= scale
+    return u, U
