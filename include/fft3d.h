@@ -252,8 +252,9 @@ int fft3d_exchange_block(int64_t n0, int64_t ncols, int64_t p, int64_t src, int6
  * r2c or c2r of `ncomp` fields of one shape and dtype (say the three
  * components of a velocity field) -- is admitted when its bytes fit in what
  * the arena has free (first come, first served: a request waits behind an
- * earlier one that does not fit yet), then launched at once on the next
- * stream: requests of at most `batch_points` real points per field go, with
+ * earlier one that does not fit yet), then launched at once on the stream
+ * with the least work in flight: requests of at most `batch_points` real
+ * points per field go, with
  * every other such request admitted in the same round, through one batched
  * launch (fft3d_batch_submit), larger ones through fft3d_r2c / fft3d_c2r per
  * field.  Requests that arrive while others run are admitted and launched as

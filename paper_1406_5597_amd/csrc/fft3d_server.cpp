@@ -9,8 +9,8 @@
 //      outputs and work buffers from the arena while they fit;
 //   3. launch: every admitted request is launched at once -- the small ones
 //      together through one batched launch per max_batch_items fields, each
-//      large one through the single-field path -- on the next of the
-//      server's streams, and an event is recorded behind it.
+//      large one through the single-field path -- on the server stream with
+//      the least estimated work in flight, and an event is recorded behind it.
 // The loop sleeps on a condition variable when nothing is in flight and polls
 // events every few microseconds otherwise.  The server uses only the public
 // entry points of the library for the transforms.
@@ -55,6 +55,8 @@ struct Req {
 
 struct Unit {
     hipEvent_t ev = nullptr;
+    int stream = 0;
+    double load = 0;  // estimated bytes the unit moves
     std::vector<int64_t> reqs;
 };
 
@@ -73,7 +75,7 @@ struct fft3d_server_s {
     void* base = nullptr;  // the arena's device region (a fake address without a device)
     fft3d::Arena arena;
     std::vector<hipStream_t> streams;
-    int next_stream = 0;
+    std::vector<double> stream_load;  // estimated bytes in flight per stream
     std::vector<hipEvent_t> free_events;
     std::map<std::tuple<int64_t, int64_t, int64_t, int>, fft3d_plan_t> plans;
     std::mutex plan_mu;  // plan creation, outside the main lock
@@ -163,10 +165,20 @@ struct fft3d_server_s {
     {
         Unit u;
         u.reqs = ids;
+        for (int64_t id : ids) {
+            const Req& q = *reqs[id];
+            u.load += (double)q.r.ncomp * (double)(2 * q.out_bytes + q.work_bytes);
+        }
         hipStream_t s = nullptr;
         if (!no_device) {
-            s = streams[(size_t)next_stream];
-            next_stream = (next_stream + 1) % (int)streams.size();
+            // the stream with the least work in flight, so that a small
+            // request does not queue behind a large one
+            size_t best = 0;
+            for (size_t i = 1; i < streams.size(); ++i)
+                if (stream_load[i] < stream_load[best]) best = i;
+            s = streams[best];
+            u.stream = (int)best;
+            stream_load[best] += u.load;
         }
         const double t = now();
         int rc = FFT3D_OK;
@@ -211,7 +223,10 @@ struct fft3d_server_s {
         if (rc != FFT3D_OK) {
             // nothing of this unit is known to run: fail its requests once the
             // stream has drained what was enqueued
-            if (!no_device) (void)hipStreamSynchronize(s);
+            if (!no_device) {
+                (void)hipStreamSynchronize(s);
+                stream_load[(size_t)u.stream] -= u.load;
+            }
             for (int64_t id : ids) finish(*reqs[id], false, why);
             if (u.ev) free_events.push_back(u.ev);
             cv_done.notify_all();
@@ -236,6 +251,7 @@ struct fft3d_server_s {
                 for (int64_t id : it->reqs)
                     finish(*reqs[id], e == hipSuccess, e == hipSuccess ? "" : hipGetErrorString(e));
                 if (it->ev) free_events.push_back(it->ev);
+                if (!no_device) stream_load[(size_t)it->stream] -= it->load;
                 it = inflight.erase(it);
                 any_done = true;
             }
@@ -346,6 +362,7 @@ int fft3d_server_create(const fft3d_server_config* cfg, fft3d_server_t* out)
             hipStream_t st = nullptr;
             if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) break;
             s->streams.push_back(st);
+            s->stream_load.push_back(0.0);
         }
         if (e != hipSuccess) {
             for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
