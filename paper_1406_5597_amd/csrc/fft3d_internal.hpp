@@ -86,6 +86,7 @@ struct Plan {
     int coop_nslots = 0;
     int coop_lag = 2;              // slots between a plane's two phases
     int64_t plane_group = 0;       // split plane step in groups of this many planes (0: all at once)
+    int n0_group = 1;              // n0-pass tiles sent together to one XCD (see plan_build_host)
     int64_t coop_ctr_count = 0;
     int* d_ctr = nullptr;
     AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h

@@ -179,12 +179,12 @@ template <typename T, int NT, int EPT, bool INV>
 __global__ __launch_bounds__(NT) void k_cols(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
                                              const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
                                              int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
-                                             int64_t ngroups, int gsize, int reverse)
+                                             int64_t ntiles, int64_t ngroups, int gsize, int reverse)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int64_t t = group_tile(blockIdx.x, ngroups, gsize, reverse);
-    if (t >= ngroups * gsize) return;  // padding workgroup
+    if (t >= ntiles) return;  // padding workgroup
     const int64_t b = t / tiles_per_batch;
     const int64_t c0 = (t - b * tiles_per_batch) * W;
     const int64_t rem = ncols - c0;
@@ -634,19 +634,19 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
     // XCD groups: the tiles of one block (plane) for a batched pass, single
     // tiles for the one-block (n0) pass
     const int64_t ntiles = cp.nbatch * cp.tiles_per_batch;
-    const int gsize = cp.nbatch > 1 ? (int)cp.tiles_per_batch : 1;
-    const int64_t ngroups = ntiles / gsize;
+    const int gsize = cp.nbatch > 1 ? (int)cp.tiles_per_batch : std::max(1, p.n0_group);
+    const int64_t ngroups = (ntiles + gsize - 1) / gsize;
     const unsigned grid = (unsigned)group_grid(ngroups, gsize);
     const cx<T>* ci = static_cast<const cx<T>*>(in);
     cx<T>* co = static_cast<cx<T>*>(out);
     if (cp.big)
         hipLaunchKernelGGL((k_cols<T, kNtBig, EB, INV>), dim3(grid), dim3(kNtBig), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
-                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ngroups, gsize, rev);
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
     else
         hipLaunchKernelGGL((k_cols<T, kNtSmall, ES, INV>), dim3(grid), dim3(kNtSmall), cp.lds, st, ci, co,
                            ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
-                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ngroups, gsize, rev);
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
     return hipGetLastError();
 }
 
