@@ -199,7 +199,11 @@ const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_l
     const int cxs = 2 * p.elem;
     const int es = kNtSmall * (p.dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
     const int eb = kNtBig * (p.dtype ? Tier<double>::kEptBig : Tier<float>::kEptBig);
-    int64_t r = std::min<int64_t>(es / p.h, kLdsHalf / ((int64_t)p.Hs * cxs));
+    // rows per tile: what the small tier holds, within an LDS budget that
+    // lets three FP32 workgroups (two FP64) share a CU -- measured at 512^3:
+    // FP32 rows kernels 4.35 -> 4.72 TB/s with 16 rows instead of 32
+    const int64_t budget = p.dtype == FFT3D_F64 ? 60 * 1024 : 48 * 1024;
+    int64_t r = std::min<int64_t>(es / p.h, budget / ((int64_t)p.Hs * cxs));
     rows_big = false;
     if (r < 1) {
         r = std::min<int64_t>(eb / p.h, kLdsMax / ((int64_t)p.Hs * cxs));
@@ -298,6 +302,24 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         if (err) {
             why = err;
             return FFT3D_ERR_UNSUPPORTED;
+        }
+        // tuning overrides: rows per rows-kernel tile (at most the tier's),
+        // n1-pass tile width (power of two, at most the tier's)
+        if (const char* v = getenv("FFT3D_ROWS_RPW")) {
+            const int r = atoi(v);
+            if (r >= 1 && r < p.rpw) {
+                p.rpw = r;
+                p.rows_lds = (size_t)(p.rpw * p.Hs * cxs);
+            }
+        }
+        if (const char* v = getenv("FFT3D_N1_W")) {
+            const int W = atoi(v);
+            if (W >= 1 && W < p.pass1.W && (W & (W - 1)) == 0) {
+                p.pass1.W = W;
+                p.pass1.wshift = ilog2(W);
+                p.pass1.tiles_per_batch = (p.H + W - 1) / W;
+                p.pass1.lds = (size_t)(n1 * W * cxs);
+            }
         }
         // one cooperative launch for the plane step when both task kinds fit
         // the small tier (and the caller did not ask for the two-kernel path)
