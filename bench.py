@@ -148,6 +148,48 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     return out, res
 
 
+def run_ablation(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
+    """The paper's comparison (Sec. 3) on one GPU: the transpose-based method
+    (Sec. 2.1: plane step, explicit n0<->n1 exchange, n0 columns of the
+    exchanged layout; inverse in reverse) against the transpose-free path
+    (Sec. 2.2) timed above, same kernels otherwise, same field."""
+    plan = F.Plan(*shape, dtype=dtype)
+    n0, n1, n2 = shape
+    x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
+    Xt = torch.empty((n1, n0, n2 // 2 + 1), dtype=F.torch_dtypes(dtype)[1], device="cuda")
+    y = F.empty_real(plan)
+    work = F.empty_complex(plan)
+    s = torch.cuda.current_stream()
+
+    def pair():
+        F.fft3d_r2c_transposed(plan, x, Xt, work, s)
+        F.fft3d_c2r_transposed(plan, Xt, y, work, s)
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(k):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms = timed(pair, steps)
+    swap_us = 1e3 * timed(lambda: F.fft3d_run_pass(plan, F.FFT3D_PASS_SWAP01, work, Xt, s), steps)
+    n0t_us = 1e3 * timed(lambda: F.fft3d_run_pass(plan, F.FFT3D_PASS_N0T_FWD, Xt, Xt, s), steps)
+    elem = 4 if dtype == "f32" else 8
+    M = n0 * n1 * (n2 // 2 + 1)
+    del x, Xt, y, work
+    return {"transpose_based_ms_per_pair": round(ms, 4), "transpose_free_ms_per_pair": round(free_ms, 4),
+            "transpose_free_speedup": round(ms / free_ms, 3),
+            "exchange_us": round(swap_us, 1), "exchange_GB_s": round(4 * elem * M / (swap_us * 1e-6) / 1e9, 1),
+            "n0_columns_exchanged_layout_us": round(n0t_us, 1)}
+
+
 def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
     32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
@@ -368,6 +410,7 @@ def main() -> int:
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the transpose-based comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s) of the served stream")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per served rate")
@@ -400,6 +443,16 @@ def main() -> int:
         print("# %s: %.3f ms/pair, %.1f pairs/s, dominant %s %.1f GB/s" % (
             d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
             results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)
+    ablation = None
+    if not args.no_ablation:
+        ablation = {}
+        for d in dtypes:
+            print("# transpose-based method %s ..." % d, file=sys.stderr, flush=True)
+            ablation[d] = run_ablation(F, torch, x64, shape, d, args.steps, args.warmup, fields,
+                                       results[d]["ms_per_pair"])
+            print("# %s: transpose-based %.3f ms/pair vs transpose-free %.3f" % (
+                d, ablation[d]["transpose_based_ms_per_pair"], results[d]["ms_per_pair"]), file=sys.stderr,
+                flush=True)
     copy_gbs = copy_bandwidth(torch)
     batch = None
     if not args.no_batch:
@@ -481,6 +534,7 @@ def main() -> int:
         "copy_GB_s": round(copy_gbs, 1),
         "batch": batch,
         "served": served,
+        "ablation_transpose": ablation,
     }
     for k in ("rel_l2_r2c", "rel_l2_c2r"):
         if k in r:

@@ -191,6 +191,18 @@ int fft3d_batch_status(fft3d_batch_t b);
 int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len);
 int fft3d_batch_destroy(fft3d_batch_t b);
 
+/* The transpose-based method of the paper's Sec. 2.1, for comparison with
+ * the transpose-free path (Sec. 2.2): step 1 (the same plane step) into
+ * `work`, step 2 an explicit exchange of the n0 and n1 axes (rows of n2/2+1
+ * complex values stay contiguous) into Xt, step 3 the n0 columns of that
+ * layout (stride n2/2+1) in place.  Xt: n1 x n0 x (n2/2+1) complex, i.e.
+ * Xt[k1][k0][k2] = X[k0][k1][k2] -- FFTW's "transposed out" order; bit for bit
+ * the transpose of fft3d_r2c's output.  work: fft3d_work_bytes(p), required.
+ * fft3d_c2r_transposed inverts it in reverse order (n0 columns of Xt into
+ * work, exchange back into Xt, plane step to y): Xt is overwritten. */
+int fft3d_r2c_transposed(fft3d_plan_t p, const void* x, void* Xt, void* work, hipStream_t stream);
+int fft3d_c2r_transposed(fft3d_plan_t p, void* Xt, void* y, void* work, hipStream_t stream);
+
 /* The passes a transform is made of, for fft3d_run_pass.  The forward
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
  * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan's
@@ -205,7 +217,12 @@ enum {
     FFT3D_PASS_N0_FWD = 2,    /* in/out: spectrum (in == out allowed); paper step 3 */
     FFT3D_PASS_N0_INV = 3,    /* in/out: spectrum (in == out allowed) */
     FFT3D_PASS_N1_INV = 4,    /* in/out: spectrum (in == out allowed) */
-    FFT3D_PASS_PLANE_C2R = 5  /* in: spectrum; out: real y */
+    FFT3D_PASS_PLANE_C2R = 5, /* in: spectrum; out: real y */
+    /* the transpose-based method (fft3d_r2c_transposed): */
+    FFT3D_PASS_SWAP01 = 6,    /* in: natural-order spectrum [n0][n1][H]; out: transposed [n1][n0][H] */
+    FFT3D_PASS_SWAP10 = 7,    /* in: transposed; out: natural order */
+    FFT3D_PASS_N0T_FWD = 8,   /* in/out: transposed spectrum (in == out allowed) */
+    FFT3D_PASS_N0T_INV = 9    /* in/out: transposed spectrum (in == out allowed) */
 };
 
 /* Enqueue one pass of the plan on `stream` (no allocation, no sync): the same

@@ -462,6 +462,63 @@ int fft3d_c2r(fft3d_plan_t h, void* X, void* y, void* work, hipStream_t s)
     return enqueue_c2r(h->p, X, y, work, s);
 }
 
+int fft3d_r2c_transposed(fft3d_plan_t h, const void* x, void* Xt, void* work, hipStream_t s)
+{
+    const char* who = "fft3d_r2c_transposed";
+    int rc = validate_r2c(h, x, Xt);
+    if (rc) return rc;
+    const fft3d::Plan& p = h->p;
+    if ((rc = check_ptr(work, 2 * p.elem, who, "work"))) return rc;
+    const size_t cb = cplx_bytes(p);
+    if (overlaps(work, cb, Xt, cb) || overlaps(work, cb, x, real_bytes(p)))
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": work overlaps x or Xt");
+    // step 1 into work: the plane step of the transpose-free path (its own
+    // n0 pass is left out)
+    hipError_t e;
+    if (p.fused_plane) {
+        e = fft3d::launch_plane_r2c(p, x, work, s);
+    } else if (p.coop) {
+        e = fft3d::launch_plane_coop(p, x, work, false, s);
+    } else {
+        e = fft3d::launch_rows_r2c(p, x, work, p.n0 * p.n1, 0, s);
+        if (e == hipSuccess && p.n1 > 1) e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, work, work, false, 1, s);
+    }
+    // step 2: the transpose; step 3: n0 columns of the transposed layout
+    if (e == hipSuccess) e = fft3d::launch_swap01(p, work, Xt, p.n0, p.n1, s);
+    if (e == hipSuccess && p.n0 > 1) e = fft3d::launch_cols(p, p.pass0t, 0, p.off_ax0, Xt, Xt, false, 1, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
+int fft3d_c2r_transposed(fft3d_plan_t h, void* Xt, void* y, void* work, hipStream_t s)
+{
+    const char* who = "fft3d_c2r_transposed";
+    int rc = validate_c2r(h, Xt, y, work);
+    if (rc) return rc;
+    if (!work) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": work is required");
+    const fft3d::Plan& p = h->p;
+    hipError_t e = hipSuccess;
+    const void* t = Xt;
+    if (p.n0 > 1) {
+        e = fft3d::launch_cols(p, p.pass0t, 0, p.off_ax0, Xt, work, true, 1, s);
+        t = work;
+    }
+    if (e == hipSuccess) e = fft3d::launch_swap01(p, t, t == work ? Xt : work, p.n1, p.n0, s);
+    void* nat = t == work ? Xt : work;  // natural-order spectrum after the exchange
+    if (e == hipSuccess) {
+        if (p.fused_plane) {
+            e = fft3d::launch_plane_c2r(p, nat, y, s);
+        } else if (p.coop) {
+            e = fft3d::launch_plane_coop(p, nat, y, true, s);
+        } else {
+            if (p.n1 > 1) e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, nat, nat, true, 1, s);
+            if (e == hipSuccess) e = fft3d::launch_rows_c2r(p, nat, y, p.n0 * p.n1, 0, s);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
 {
     return fft3d_batch_submit_ex(items, n, 0, s);
@@ -652,6 +709,19 @@ int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStrea
         if (in != out && overlaps(in, cb, out, cb))
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
         e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV, 0, s);
+        break;
+    case FFT3D_PASS_SWAP01:
+    case FFT3D_PASS_SWAP10:
+        if (overlaps(in, cb, out, cb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
+        e = pass == FFT3D_PASS_SWAP01 ? fft3d::launch_swap01(p, in, out, p.n0, p.n1, s)
+                                      : fft3d::launch_swap01(p, in, out, p.n1, p.n0, s);
+        break;
+    case FFT3D_PASS_N0T_FWD:
+    case FFT3D_PASS_N0T_INV:
+        if (p.n0 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n0 pass");
+        if (in != out && overlaps(in, cb, out, cb))
+            return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
+        e = fft3d::launch_cols(p, p.pass0t, 0, p.off_ax0, in, out, pass == FFT3D_PASS_N0T_INV, 1, s);
         break;
     default: return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: unknown pass");
     }

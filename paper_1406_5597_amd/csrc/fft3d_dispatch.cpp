@@ -44,6 +44,10 @@ hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inve
 {
     return p.dtype ? launch_plane_coop_f64(p, in, out, inverse, st) : launch_plane_coop_f32(p, in, out, inverse, st);
 }
+hipError_t launch_swap01(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t st)
+{
+    return p.dtype ? launch_swap01_f64(p, in, out, na, nb, st) : launch_swap01_f32(p, in, out, na, nb, st);
+}
 hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st)
 {
     return p.dtype ? launch_plane_r2c_f64(p, x, X, st) : launch_plane_r2c_f32(p, x, X, st);

@@ -76,6 +76,7 @@ struct Plan {
     size_t rows_lds = 0;
     ColPass pass1;             // n1 columns of each plane (split)
     ColPass pass0;             // n0 columns over C (the strided step)
+    ColPass pass0t;            // n0 columns of the transposed layout [n1][n0][H] (transpose-based method)
 
     // cooperative plane step (split planes done in one launch, see k_plane_coop)
     bool coop = false;
@@ -135,7 +136,8 @@ constexpr int kCoopQueues = 16;
     hipError_t launch_rows_c2r_##sfx(const Plan& p, const void* X, void* y, int64_t nrows, int rev,        \
                                      hipStream_t s);                                                       \
     hipError_t launch_cols_##sfx(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, \
-                                 void* out, bool inverse, int rev, hipStream_t s);
+                                 void* out, bool inverse, int rev, hipStream_t s);                         \
+    hipError_t launch_swap01_##sfx(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t s);
 FFT3D_DECLARE_DTYPE(f32)
 FFT3D_DECLARE_DTYPE(f64)
 #undef FFT3D_DECLARE_DTYPE
@@ -151,6 +153,9 @@ hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows,
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t stream);
 hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inverse, hipStream_t stream);
+// Exchange of the two outer axes of an [na][nb][H] array of complex rows
+// (the explicit transpose of the transpose-based method).
+hipError_t launch_swap01(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t stream);
 // The message fft3d_last_error() returns on this thread.
 void set_last_error(const std::string& m);
 // Raise the dynamic-LDS limit of every kernel once per process.

@@ -28,4 +28,9 @@ hipError_t launch_cols_f32(const Plan& p, const ColPass& cp, int axis, int64_t t
                    : cols_t<float, false>(p, cp, axis, tw_off, in, out, rev, s);
 }
 
+hipError_t launch_swap01_f32(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t s)
+{
+    return swap01_t<float>(p, in, out, na, nb, s);
+}
+
 }  // namespace fft3d

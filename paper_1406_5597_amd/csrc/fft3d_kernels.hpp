@@ -17,6 +17,8 @@
 // one contiguous W-element segment of memory.
 #pragma once
 
+#include <algorithm>
+
 #include "fft3d_device.hpp"
 #include "fft3d_internal.hpp"
 
@@ -494,6 +496,40 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
+// Exchange of the two outer axes of an [na][nb][H] array of rows (the
+// transpose of the paper's transpose-based method, Sec. 2.1 step 2):
+// out[b][a][:] = in[a][b][:].  Rows of H elements stay contiguous, so reads
+// and writes are whole-row runs.  Workgroup: rows a0 .. a0+R-1 of column b,
+// written as one contiguous run.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_swap01(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int na,
+                                              int nb, int H, int R, uint32_t mgH, int tiles_a)
+{
+    constexpr int U = 8;
+    const int b = (int)blockIdx.x / tiles_a;
+    const int a0 = ((int)blockIdx.x - b * tiles_a) * R;
+    const int rows = na - a0 < R ? na - a0 : R;
+    const int count = rows * H;
+    const int64_t stride = (int64_t)nb * H;
+    const cx<T>* src = in + ((int64_t)a0 * nb + b) * H;
+    cx<T>* dst = out + ((int64_t)b * na + a0) * H;
+    for (int base = 0; base < count; base += U * NT) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int e = base + (int)threadIdx.x + u * NT;
+            e = e < count ? e : count - 1;  // always a valid address
+            const int q = fdiv(e, mgH);
+            v[u] = load_cx<LD_STREAM, T>(src + q * stride + (e - q * H));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            if (e < count) store_cx<ST_STREAM, T>(dst + e, v[u]);
+        }
+    }
+}
+
 template <int Unused = 0> __global__ void k_zero_ints(int* p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -647,6 +683,19 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
         hipLaunchKernelGGL((k_cols<T, kNtSmall, ES, INV>), dim3(grid), dim3(kNtSmall), cp.lds, st, ci, co,
                            ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
+    return hipGetLastError();
+}
+
+// in: [na][nb][H] -> out: [nb][na][H]
+template <typename T>
+hipError_t swap01_t(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t st)
+{
+    const int H = (int)p.H;
+    const int R = std::max(1, 8192 / H);
+    const int tiles_a = (int)((na + R - 1) / R);
+    const unsigned grid = (unsigned)(nb * tiles_a);
+    hipLaunchKernelGGL((k_swap01<T, kNtSmall>), dim3(grid), dim3(kNtSmall), 0, st, static_cast<const cx<T>*>(in),
+                       static_cast<cx<T>*>(out), (int)na, (int)nb, H, R, div_magic((uint32_t)H), tiles_a);
     return hipGetLastError();
 }
 

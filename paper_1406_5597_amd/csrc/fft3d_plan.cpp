@@ -349,6 +349,12 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         why = "n0 too large for a column tile";
         return FFT3D_ERR_UNSUPPORTED;
     }
+    // the n0 pass of the transpose-based method: length-n0 columns of the
+    // [n1][n0][H] layout, one block per k1
+    if (!make_colpass(p.pass0t, n0, p.H, p.H, n1, n0 * p.H, cxs, es, eb)) {
+        why = "n0 too large for a column tile";
+        return FFT3D_ERR_UNSUPPORTED;
+    }
     // n0-pass tiles per XCD group: neighbouring column tiles read and write
     // neighbouring 128-byte segments of every row; keeping 8 (FP32) / 16
     // (FP64) of them on one XCD measured 1.5-3% faster pairs at 512^3

@@ -35,6 +35,10 @@ FFT3D_PASS_N0_FWD = 2
 FFT3D_PASS_N0_INV = 3
 FFT3D_PASS_N1_INV = 4
 FFT3D_PASS_PLANE_C2R = 5
+FFT3D_PASS_SWAP01 = 6
+FFT3D_PASS_SWAP10 = 7
+FFT3D_PASS_N0T_FWD = 8
+FFT3D_PASS_N0T_INV = 9
 FFT3D_BATCH_SEQUENTIAL = 2
 FFT3D_BATCH_DIRECT = 4
 FFT3D_SERVER_NO_DEVICE = 1
@@ -48,7 +52,8 @@ EXPORTS = (
     "fft3d_exchange_block", "fft3d_run_pass", "fft3d_batch_submit_ex", "fft3d_batch_create",
     "fft3d_batch_launch", "fft3d_batch_status", "fft3d_batch_describe", "fft3d_batch_destroy",
     "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
-    "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy",
+    "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy", "fft3d_r2c_transposed",
+    "fft3d_c2r_transposed",
 )
 
 
@@ -116,6 +121,8 @@ def _load() -> ctypes.CDLL:
         "fft3d_server_release": (ctypes.c_int, [vp, i64]),
         "fft3d_server_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerCounters)]),
         "fft3d_server_destroy": (ctypes.c_int, [vp]),
+        "fft3d_r2c_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fft3d_c2r_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -259,6 +266,14 @@ def _items(items):
     for i, (plan, d, a, m, o, w) in enumerate(items):
         arr[i] = BatchItem(plan.handle, d, _addr(a), _addr(m), _addr(o), _addr(w))
     return arr
+
+
+def fft3d_r2c_transposed(plan: Plan, x, Xt, work, stream=None) -> None:
+    _check(lib.fft3d_r2c_transposed(plan.handle, _addr(x), _addr(Xt), _addr(work), _stream(stream)))
+
+
+def fft3d_c2r_transposed(plan: Plan, Xt, y, work, stream=None) -> None:
+    _check(lib.fft3d_c2r_transposed(plan.handle, _addr(Xt), _addr(y), _addr(work), _stream(stream)))
 
 
 def fft3d_batch_submit(items, stream=None) -> None:

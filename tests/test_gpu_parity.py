@@ -214,3 +214,43 @@ def test_batch_submit_matches_alone(F):
     for (X1, y1), (mid, y) in zip(alone, outs):
         assert bool((mid == X1).all())
         assert bool((y == y1).all())
+
+
+TRANSPOSED_SHAPES = [(2, 3, 4), (1, 8, 16), (8, 1, 8), (12, 9, 24), (32, 32, 32), (48, 36, 64), (96, 64, 32),
+                     (24, 256, 256), (128, 128, 128), (3, 1024, 1024)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", TRANSPOSED_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_transpose_based_method(F, oracle, shape, dtype):
+    """The paper's transpose-based method (plane step, explicit n0<->n1
+    exchange, contiguous-in-slab n0 columns) gives the transpose of the
+    transpose-free spectrum bit for bit, and its inverse the same real field."""
+    import torch
+    say("transposed %s %s" % (shape, dtype))
+    n0, n1, n2 = shape
+    x = rounded(fields.uniform(shape, seed=77), dtype)
+    plan = F.Plan(*shape, dtype=dtype)
+    xd = dev_real(x, dtype)
+    X = F.r2c(plan, xd)
+    Xt = torch.empty((n1, n0, n2 // 2 + 1), dtype=X.dtype, device="cuda")
+    work = F.empty_complex(plan)
+    F.fft3d_r2c_transposed(plan, xd, Xt, work)
+    torch.cuda.synchronize()
+    assert bool((Xt == X.permute(1, 0, 2)).all()), "transposed spectrum differs from the transpose-free one"
+    assert rel_l2(host(Xt).transpose(1, 0, 2), oracle.r2c(x)) <= TOL[dtype]
+    y_free = F.c2r(plan, X.clone(), work=F.empty_complex(plan))
+    y = F.empty_real(plan)
+    F.fft3d_c2r_transposed(plan, Xt, y, work)
+    torch.cuda.synchronize()
+    assert bool((y == y_free).all()), "transposed inverse differs"
+
+
+def test_transposed_needs_work(F):
+    p = F.Plan(8, 8, 8, dtype="f32")
+    x = dev_real(fields.uniform((8, 8, 8), 1), "f32")
+    Xt = F.empty_complex(p)
+    with pytest.raises(F.Fft3dError):
+        F.fft3d_r2c_transposed(p, x, Xt, None)
+    with pytest.raises(F.Fft3dError):
+        F.fft3d_c2r_transposed(p, Xt, F.empty_real(p), None)
