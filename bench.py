@@ -480,14 +480,19 @@ def main() -> int:
         head = dtypes[0]
         plan, x, X, y = keep[head]
         xin = fields.as_dtype(x64, head).astype(np.float64)
-        print("# oracle sample (one %s pair, FP64) ..." % (shape,), file=sys.stderr, flush=True)
+        print("# oracle sample (%s pairs, FP64, about 10 s) ..." % (shape,), file=sys.stderr, flush=True)
         t0 = time.time()
-        Xo = oracle.r2c(xin)
-        yo = oracle.c2r(Xo, n)
+        pairs = 0
+        while True:
+            Xo = oracle.r2c(xin)
+            yo = oracle.c2r(Xo, n)
+            pairs += 1
+            if time.time() - t0 >= 10.0 or pairs >= 8:
+                break
         dt = time.time() - t0
-        cpu = {"value": 1.0 / dt, "unit": "pairs/s", "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": "one r2c+c2r pair of the same %dx%dx%d field (%s-rounded input, computed in FP64), "
-                         "%.1f s wall" % (n, n, n, head, dt)}
+        cpu = {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "%d r2c+c2r pairs of the same %dx%dx%d field (%s-rounded input, computed in FP64), "
+                         "%.1f s wall" % (pairs, n, n, n, head, dt)}
         for d in dtypes:
             p, xd, Xd, yd = keep[d]
             if d != head:
