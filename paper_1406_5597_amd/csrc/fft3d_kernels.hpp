@@ -77,11 +77,39 @@ __device__ __forceinline__ LdsPlaneColsIO<T> lds_plane_cols(cx<T>* buf, int n1, 
 
 // `rows` contiguous rows of H elements in global memory <-> padded LDS rows,
 // 8 loads in flight per thread before the matching stores.  mgH: div_magic(H).
+// FP32: two complex values (16 bytes) per lane and access when the run is
+// 16-byte aligned and of even length (the usual case), which halves the
+// memory instructions.
 template <typename T, int NT, int LP = LD_PLAIN>
 __device__ __forceinline__ void rows_to_lds(cx<T>* buf, const cx<T>* src, int rows, int H, int Hs, uint32_t mgH)
 {
     constexpr int U = 8;
     const int count = rows * H;
+    if constexpr (sizeof(T) == 4 && LP == LD_PLAIN) {
+        if (((uintptr_t)src & 15) == 0 && (count & 1) == 0) {
+            const int pairs = count >> 1;
+            const float4* s4 = reinterpret_cast<const float4*>(src);
+            for (int base = 0; base < pairs; base += U * NT) {
+                float4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = base + (int)threadIdx.x + u * NT;
+                    v[u] = s4[e < pairs ? e : pairs - 1];  // always a valid address
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = base + (int)threadIdx.x + u * NT;
+                    if (e < pairs) {
+                        const int e0 = 2 * e, e1 = e0 + 1;
+                        const int q0 = fdiv(e0, mgH), q1 = fdiv(e1, mgH);
+                        buf[q0 * Hs + pad16(e0 - q0 * H)] = mk<T>(v[u].x, v[u].y);
+                        buf[q1 * Hs + pad16(e1 - q1 * H)] = mk<T>(v[u].z, v[u].w);
+                    }
+                }
+            }
+            return;
+        }
+    }
     for (int base = 0; base < count; base += U * NT) {
         cx<T> v[U];
 #pragma unroll
@@ -104,6 +132,19 @@ template <typename T, int NT, int SP = ST_PLAIN>
 __device__ __forceinline__ void lds_to_rows(cx<T>* dst, const cx<T>* buf, int rows, int H, int Hs, uint32_t mgH)
 {
     const int count = rows * H;
+    if constexpr (sizeof(T) == 4 && SP == ST_PLAIN) {
+        if (((uintptr_t)dst & 15) == 0 && (count & 1) == 0) {
+            const int pairs = count >> 1;
+            float4* d4 = reinterpret_cast<float4*>(dst);
+            for (int e = (int)threadIdx.x; e < pairs; e += NT) {
+                const int e0 = 2 * e, e1 = e0 + 1;
+                const int q0 = fdiv(e0, mgH), q1 = fdiv(e1, mgH);
+                const cx<T> a = buf[q0 * Hs + pad16(e0 - q0 * H)], b = buf[q1 * Hs + pad16(e1 - q1 * H)];
+                d4[e] = make_float4(a.x, a.y, b.x, b.y);
+            }
+            return;
+        }
+    }
     for (int e = (int)threadIdx.x; e < count; e += NT) {
         const int q = fdiv(e, mgH);
         store_cx<SP, T>(dst + e, buf[q * Hs + pad16(e - q * H)]);
