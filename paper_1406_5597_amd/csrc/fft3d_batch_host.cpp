@@ -80,7 +80,8 @@ const char* item_tiling(const Plan& p, ItemTiling& t)
     const bool widen = batch_widen();
     if (p.n0 > 1) {
         t.pass0 = p.pass0;
-        if (t.pass0.big && !small_colpass(p, 0, t.pass0)) return "n0 too long for a small-tier column tile";
+        if ((t.pass0.big || t.pass0.wide) && !small_colpass(p, 0, t.pass0))
+            return "n0 too long for a small-tier column tile";
         if (widen) widen_cols(t.pass0, p.n0, p);
     }
     if (p.fused_plane && !p.plane_big && p.plane_lds <= kBatchLdsCap) {
@@ -114,7 +115,8 @@ const char* item_tiling(const Plan& p, ItemTiling& t)
         if (t.rpw < 1) return "rows too long for a small-tier tile";
         t.rows_lds = (size_t)(t.rpw * row_bytes);
     }
-    if (p.n1 > 1 && t.pass1.big && !small_colpass(p, 1, t.pass1)) return "n1 too long for a small-tier column tile";
+    if (p.n1 > 1 && (t.pass1.big || t.pass1.wide) && !small_colpass(p, 1, t.pass1))
+        return "n1 too long for a small-tier column tile";
     if (p.n1 > 1 && widen) widen_cols(t.pass1, p.n1, p);
     return nullptr;
 }

@@ -24,6 +24,10 @@ constexpr int kLdsHalf = 80 * 1024;
 // whole 160 KB of LDS.
 constexpr int kNtSmall = 512;
 constexpr int kNtBig = 512;
+// Wide tier of the column kernels: the small tier's elements per thread on
+// 1024 threads -- tiles as large as 128 KB (long columns at full 128-byte
+// width) at the small tier's register budget, sixteen waves per CU.
+constexpr int kNtWide = 1024;
 template <typename T> struct Tier;
 template <> struct Tier<float> {
     static constexpr int kEptSmall = 16;  // 8192 elements, 64 KB
@@ -45,7 +49,8 @@ struct ColPass {
     int W = 0;            // tile width (power of two)
     int wshift = 0;       // log2(W)
     int64_t tiles_per_batch = 0;
-    bool big = false;     // kernel tier
+    bool big = false;     // kernel tier: big, or
+    bool wide = false;    // ... wide (column kernels only), else small
     size_t lds = 0;       // dynamic LDS bytes
 };
 

@@ -610,6 +610,8 @@ template <typename T> hipError_t init_plain()
     FFT3D_ALLOW((k_cols<T, kNtSmall, ES, true>));
     FFT3D_ALLOW((k_cols<T, kNtBig, EB, false>));
     FFT3D_ALLOW((k_cols<T, kNtBig, EB, true>));
+    FFT3D_ALLOW((k_cols<T, kNtWide, ES, false>));
+    FFT3D_ALLOW((k_cols<T, kNtWide, ES, true>));
     FFT3D_ALLOW((k_rows_r2c<T, kNtSmall, ES>));
     FFT3D_ALLOW((k_rows_r2c<T, kNtBig, EB>));
     FFT3D_ALLOW((k_rows_c2r<T, kNtSmall, ES>));
@@ -718,6 +720,10 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
     cx<T>* co = static_cast<cx<T>*>(out);
     if (cp.big)
         hipLaunchKernelGGL((k_cols<T, kNtBig, EB, INV>), dim3(grid), dim3(kNtBig), cp.lds, st, ci, co, ax,
+                           table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
+                           div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
+    else if (cp.wide)
+        hipLaunchKernelGGL((k_cols<T, kNtWide, ES, INV>), dim3(grid), dim3(kNtWide), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
     else

@@ -161,13 +161,17 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     while (cap < ncols && cap < 64) cap *= 2;
     int W = std::min<int64_t>(target, cap);
     while (W < 64 && W < cap && n * W < 2048 && n * W * 2 <= es) W *= 2;
-    bool big = false;
+    bool big = false, wide = false;
+    const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
     if (!allow_big) {
         while (W > 1 && n * W > es) W /= 2;
         if (n * W > es || n * W * cxs > kLdsHalf) return false;
     } else if (n * W > es) {
-        // prefer the big tier at the target width over narrow segments
-        if (n * W <= eb && n * W * cxs <= kLdsMax) {
+        // prefer a larger tier at the target width over narrow segments: the
+        // wide one (same registers per thread) if it holds the tile, else big
+        if (n * W <= ew && n * W * cxs <= kLdsMax) {
+            wide = true;
+        } else if (n * W <= eb && n * W * cxs <= kLdsMax) {
             big = true;
         } else {
             while (W > 1 && n * W > es) W /= 2;
@@ -181,6 +185,7 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     cp.W = W;
     cp.wshift = ilog2(W);
     cp.big = big;
+    cp.wide = wide;
     cp.tiles_per_batch = (ncols + W - 1) / W;
     cp.lds = (size_t)(n * W * cxs);
     return true;
@@ -315,6 +320,10 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         if (const char* v = getenv("FFT3D_N1_W")) {
             const int W = atoi(v);
             if (W >= 1 && W < p.pass1.W && (W & (W - 1)) == 0) {
+                const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
+                const bool over = n1 * W > es || n1 * W * cxs > kLdsHalf;
+                p.pass1.wide = over && n1 * W <= ew;
+                p.pass1.big = over && !p.pass1.wide;
                 p.pass1.W = W;
                 p.pass1.wshift = ilog2(W);
                 p.pass1.tiles_per_batch = (p.H + W - 1) / W;
@@ -323,7 +332,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         }
         // one cooperative launch for the plane step when both task kinds fit
         // the small tier (and the caller did not ask for the two-kernel path)
-        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && n1 > 1) {
+        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1) {
             p.coop = true;
             p.coop_rpw = p.rpw;
             p.coop_w = p.pass1.W;
@@ -368,7 +377,10 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         if (W >= 1 && (W & (W - 1)) == 0 && n0 * W <= eb && n0 * W * cxs <= kLdsMax) {
             cp.W = W;
             cp.wshift = ilog2(W);
-            cp.big = n0 * W > es || n0 * W * cxs > kLdsHalf;
+            const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
+            const bool over = n0 * W > es || n0 * W * cxs > kLdsHalf;
+            cp.wide = over && n0 * W <= ew;
+            cp.big = over && !cp.wide;
             cp.tiles_per_batch = (p.C + W - 1) / W;
             cp.lds = (size_t)(n0 * W * cxs);
             p.pass0 = cp;
@@ -393,7 +405,7 @@ static std::string pass_json(const ColPass& c)
              "{\"row_stride\": %lld, \"ncols\": %lld, \"nbatch\": %lld, \"batch_stride\": %lld, "
              "\"W\": %d, \"tier\": \"%s\", \"grid\": %lld, \"lds\": %zu}",
              (long long)c.S, (long long)c.ncols, (long long)c.nbatch, (long long)c.bstride, c.W,
-             c.big ? "big" : "small", (long long)(c.nbatch * c.tiles_per_batch), c.lds);
+             c.big ? "big" : (c.wide ? "wide" : "small"), (long long)(c.nbatch * c.tiles_per_batch), c.lds);
     return b;
 }
 
