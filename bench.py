@@ -190,6 +190,56 @@ def run_ablation(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
             "n0_columns_exchanged_layout_us": round(n0t_us, 1)}
 
 
+def pruned_pair_bytes_alg(shape, elem: int, kmax) -> int:
+    """Algorithmic HBM bytes of a pruned pair on the split plane path: each
+    pass reads and writes only the lines and rows inside the box (forward:
+    rows write K2+1 bins, the n1 pass keeps 2K1+1 rows, the n0 pass 2K0+1;
+    the inverse mirrors it)."""
+    n0, n1, n2 = shape
+    K0, K1, K2 = kmax
+    hw = n2 // 2 + 1 if K2 < 0 or K2 >= n2 // 2 else K2 + 1
+    m1 = n1 if K1 < 0 or 2 * K1 + 1 >= n1 else 2 * K1 + 1
+    m0 = n0 if K0 < 0 or 2 * K0 + 1 >= n0 else 2 * K0 + 1
+    c = 2 * elem
+    fwd = elem * n0 * n1 * n2 + c * (n0 * n1 * hw + n0 * n1 * hw + n0 * m1 * hw + n0 * m1 * hw + m0 * m1 * hw)
+    return 2 * fwd
+
+
+def run_pruned(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
+    """Pruned pair (forward writes, inverse reads, only the two-thirds box
+    |k| <= n/3) against the full pair timed above, same field."""
+    plan = F.Plan(*shape, dtype=dtype)
+    kmax = tuple(n // 3 for n in shape)
+    x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
+    X = F.empty_complex(plan)
+    y = F.empty_real(plan)
+    work = F.empty_complex(plan)
+    s = torch.cuda.current_stream()
+
+    def pair():
+        F.fft3d_r2c_pruned(plan, x, X, kmax, s)
+        F.fft3d_c2r_pruned(plan, X, y, kmax, work, s)
+
+    for _ in range(warmup):
+        pair()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        pair()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    elem = 4 if dtype == "f32" else 8
+    b = pruned_pair_bytes_alg(shape, elem, kmax)
+    del x, X, y, work
+    return {"kmax": list(kmax), "ms_per_pair": round(ms, 4), "pairs_s": round(1e3 / ms, 2),
+            "full_ms_per_pair": round(free_ms, 4), "speedup_vs_full": round(free_ms / ms, 3),
+            "bytes_alg": b, "bytes_ratio_vs_full": round(b / pair_bytes_alg(shape, elem), 3),
+            "GB_s_alg": round(b / (ms * 1e-3) / 1e9, 1)}
+
+
 def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
     32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
@@ -412,6 +462,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the transpose-based comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--no-pruned", action="store_true", help="skip the pruned (two-thirds box) pair")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s) of the served stream")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per served rate")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="seconds of unmeasured arrivals first")
@@ -453,6 +504,16 @@ def main() -> int:
             print("# %s: transpose-based %.3f ms/pair vs transpose-free %.3f" % (
                 d, ablation[d]["transpose_based_ms_per_pair"], results[d]["ms_per_pair"]), file=sys.stderr,
                 flush=True)
+    pruned = None
+    if not args.no_pruned:
+        pruned = {}
+        for d in dtypes:
+            print("# pruned pair %s ..." % d, file=sys.stderr, flush=True)
+            pruned[d] = run_pruned(F, torch, x64, shape, d, args.steps, args.warmup, fields,
+                                   results[d]["ms_per_pair"])
+            print("# %s: pruned %.3f ms/pair vs full %.3f (%.2fx), %.1f GB/s alg" % (
+                d, pruned[d]["ms_per_pair"], results[d]["ms_per_pair"], pruned[d]["speedup_vs_full"],
+                pruned[d]["GB_s_alg"]), file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth(torch)
     batch = None
     if not args.no_batch:
@@ -540,6 +601,7 @@ def main() -> int:
         "batch": batch,
         "served": served,
         "ablation_transpose": ablation,
+        "pruned_two_thirds": pruned,
     }
     for k in ("rel_l2_r2c", "rel_l2_c2r"):
         if k in r:

@@ -203,6 +203,27 @@ int fft3d_batch_destroy(fft3d_batch_t b);
 int fft3d_r2c_transposed(fft3d_plan_t p, const void* x, void* Xt, void* work, hipStream_t stream);
 int fft3d_c2r_transposed(fft3d_plan_t p, void* Xt, void* y, void* work, hipStream_t stream);
 
+/* Pruned transforms for the dealiased pseudo-spectral solver the path serves
+ * (Sec. 1): the solver keeps only the modes of a box -- with the two-thirds
+ * rule, |k| <= n/3 on every axis -- and sets the rest to zero, so its forward
+ * transforms need only the box's modes and its inverse transforms read only
+ * those.  kmax = {K0, K1, K2} (host array) keeps |k0| <= K0, |k1| <= K1 (the
+ * signed index: k for k <= n/2, k - n above) and 0 <= k2 <= K2.  K0 or K1
+ * negative, or with 2K+1 >= n, keeps that whole axis; K2 negative or >= n2/2
+ * keeps every bin.  Every pass skips the lines and rows outside the box, so
+ * the pair moves fewer bytes (about 41% fewer at 512^3 with K = n/3).
+ *   fft3d_r2c_pruned: X holds fft3d_r2c's values on the kept modes, bit for
+ *     bit; its other elements are unspecified (what X held, or intermediate
+ *     values of the passes): the caller treats them as zero.
+ *   fft3d_c2r_pruned: y = fft3d_c2r of the spectrum that equals X on the kept
+ *     modes and is zero elsewhere (equal value for value); X's elements
+ *     outside the box are never read.  With work (fft3d_work_bytes), X is
+ *     left unchanged; without, X is overwritten.
+ * Arguments, alignment and overlap rules, and errors as fft3d_r2c /
+ * fft3d_c2r; a NULL kmax is FFT3D_ERR_INVALID_ARG. */
+int fft3d_r2c_pruned(fft3d_plan_t p, const void* x, void* X, const int64_t kmax[3], hipStream_t stream);
+int fft3d_c2r_pruned(fft3d_plan_t p, void* X, void* y, void* work, const int64_t kmax[3], hipStream_t stream);
+
 /* The passes a transform is made of, for fft3d_run_pass.  The forward
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
  * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan's

@@ -174,3 +174,44 @@ def c2r_point(X, n2: int, j) -> float:
     _check(lib().oracle_c2r_point(n0, n1, n2, _ptr(X.view(np.float64)), int(j[0]), int(j[1]),
                                   int(j[2]), _ptr(out)), "oracle_c2r_point")
     return float(out[0])
+
+
+# ---- pruned transforms (the dealiased solver's view of the transform) ----
+#
+# The pseudo-spectral solver the transform serves (Sec. 1) keeps only the
+# modes inside a box and treats the rest as zero (with the two-thirds rule,
+# |k| <= n/3 per axis).  A pruned forward transform is the forward transform
+# restricted to the box; a pruned inverse is the inverse of the spectrum
+# zeroed outside it.  Both are plain definitions on top of r2c / c2r.
+
+def box_mask(shape, kmax) -> np.ndarray:
+    """Boolean n0 x n1 x (n2/2+1) mask of the kept modes: |k0| <= K0,
+    |k1| <= K1 (signed index k or k - n), 0 <= k2 <= K2.  A negative K keeps
+    the whole axis."""
+    n0, n1, n2 = shape
+    K0, K1, K2 = (int(v) for v in kmax)
+
+    def keep(n, K):
+        i = np.arange(n)
+        s = np.where(i <= n // 2, i, i - n)  # signed index
+        return np.ones(n, bool) if K < 0 else np.abs(s) <= K
+
+    k2 = np.arange(half(n2))
+    m2 = np.ones(half(n2), bool) if K2 < 0 else k2 <= K2
+    return keep(n0, K0)[:, None, None] & keep(n1, K1)[None, :, None] & m2[None, None, :]
+
+
+def r2c_pruned(x, kmax, threads: int = 0) -> np.ndarray:
+    """Forward transform with every mode outside the box set to zero."""
+    X = r2c(x, threads)
+    X[~box_mask(np.shape(x), kmax)] = 0
+    return X
+
+
+def c2r_pruned(X, n2: int, kmax, threads: int = 0) -> np.ndarray:
+    """Inverse transform of X with every mode outside the box set to zero
+    (X is not modified)."""
+    X = np.array(_cplx(X), copy=True)
+    n0, n1, _ = X.shape
+    X[~box_mask((n0, n1, n2), kmax)] = 0
+    return c2r(X, n2, threads)

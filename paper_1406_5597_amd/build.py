@@ -34,6 +34,8 @@ SOURCES = [
     ("fft3d_kern_f32.hip", DEVICE_FLAGS),
     ("fft3d_kern_f64.hip", DEVICE_FLAGS),
     ("fft3d_batch.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f32.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f64.hip", DEVICE_FLAGS),
     ("fft3d_batch_host.cpp", HOST_FLAGS),
     ("fft3d_server.cpp", HOST_FLAGS),
     ("fft3d_plan.cpp", HOST_FLAGS),

@@ -519,6 +519,45 @@ int fft3d_c2r_transposed(fft3d_plan_t h, void* Xt, void* y, void* work, hipStrea
     return FFT3D_OK;
 }
 
+namespace {
+
+// kmax -> the kernels' box: an axis whose cut keeps every index is not cut.
+int pruned_box(const fft3d::Plan& p, const int64_t* kmax, const char* who, fft3d::PrunedBox& b)
+{
+    if (!kmax) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": kmax is NULL");
+    const int64_t K0 = kmax[0], K1 = kmax[1], K2 = kmax[2];
+    b.K0 = (K0 < 0 || 2 * K0 + 1 >= p.n0) ? -1 : (int)K0;
+    b.K1 = (K1 < 0 || 2 * K1 + 1 >= p.n1) ? -1 : (int)K1;
+    b.K2 = (K2 < 0 || K2 >= p.h) ? (int)p.h : (int)K2;
+    return FFT3D_OK;
+}
+
+}  // namespace
+
+int fft3d_r2c_pruned(fft3d_plan_t h, const void* x, void* X, const int64_t kmax[3], hipStream_t s)
+{
+    const char* who = "fft3d_r2c_pruned";
+    int rc = validate_r2c(h, x, X);
+    if (rc) return rc;
+    fft3d::PrunedBox b;
+    if ((rc = pruned_box(h->p, kmax, who, b))) return rc;
+    const hipError_t e = fft3d::launch_pruned_r2c(h->p, x, X, b, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
+int fft3d_c2r_pruned(fft3d_plan_t h, void* X, void* y, void* work, const int64_t kmax[3], hipStream_t s)
+{
+    const char* who = "fft3d_c2r_pruned";
+    int rc = validate_c2r(h, X, y, work);
+    if (rc) return rc;
+    fft3d::PrunedBox b;
+    if ((rc = pruned_box(h->p, kmax, who, b))) return rc;
+    const hipError_t e = fft3d::launch_pruned_c2r(h->p, X, y, work, b, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
 {
     return fft3d_batch_submit_ex(items, n, 0, s);

@@ -35,6 +35,8 @@ hipError_t kernels_init()
     (void)init_plain_f64();
     (void)init_coop_f32();
     (void)init_coop_f64();
+    (void)init_pruned_f32();
+    (void)init_pruned_f64();
     (void)init_batch();
     (void)hipGetLastError();
     return hipSuccess;
@@ -47,6 +49,15 @@ hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inve
 hipError_t launch_swap01(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t st)
 {
     return p.dtype ? launch_swap01_f64(p, in, out, na, nb, st) : launch_swap01_f32(p, in, out, na, nb, st);
+}
+hipError_t launch_pruned_r2c(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t st)
+{
+    return p.dtype ? launch_pruned_r2c_f64(p, x, X, b, st) : launch_pruned_r2c_f32(p, x, X, b, st);
+}
+hipError_t launch_pruned_c2r(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,
+                             hipStream_t st)
+{
+    return p.dtype ? launch_pruned_c2r_f64(p, X, y, work, b, st) : launch_pruned_c2r_f32(p, X, y, work, b, st);
 }
 hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st)
 {

@@ -128,7 +128,13 @@ void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s);
 // queue index is the hardware XCC id masked to this many).
 constexpr int kCoopQueues = 16;
 
-// Per-dtype entry points (fft3d_kern_*.hip, fft3d_coop_*.hip).
+// Box of kept modes of the pruned transforms: |k0| <= K0, |k1| <= K1,
+// 0 <= k2 <= K2.  K0, K1 < 0 keep the whole axis; K2 is in [0, h].
+struct PrunedBox {
+    int K0 = -1, K1 = -1, K2 = 0;
+};
+
+// Per-dtype entry points (fft3d_kern_*.hip, fft3d_coop_*.hip, fft3d_pruned_*.hip).
 #define FFT3D_DECLARE_DTYPE(sfx)                                                                            \
     hipError_t init_plain_##sfx();                                                                         \
     hipError_t init_coop_##sfx();                                                                          \
@@ -142,7 +148,11 @@ constexpr int kCoopQueues = 16;
                                      hipStream_t s);                                                       \
     hipError_t launch_cols_##sfx(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, \
                                  void* out, bool inverse, int rev, hipStream_t s);                         \
-    hipError_t launch_swap01_##sfx(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t s);
+    hipError_t launch_swap01_##sfx(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t s); \
+    hipError_t init_pruned_##sfx();                                                                        \
+    hipError_t launch_pruned_r2c_##sfx(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t s); \
+    hipError_t launch_pruned_c2r_##sfx(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,   \
+                                       hipStream_t s);
 FFT3D_DECLARE_DTYPE(f32)
 FFT3D_DECLARE_DTYPE(f64)
 #undef FFT3D_DECLARE_DTYPE
@@ -161,6 +171,11 @@ hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inve
 // Exchange of the two outer axes of an [na][nb][H] array of complex rows
 // (the explicit transpose of the transpose-based method).
 hipError_t launch_swap01(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t stream);
+// Pruned transforms (the whole path, enqueued): forward writes the kept box
+// of X only; inverse reads the kept box of X only (see fft3d_pruned.hpp).
+hipError_t launch_pruned_r2c(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t stream);
+hipError_t launch_pruned_c2r(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,
+                             hipStream_t stream);
 // The message fft3d_last_error() returns on this thread.
 void set_last_error(const std::string& m);
 // Raise the dynamic-LDS limit of every kernel once per process.

@@ -53,7 +53,7 @@ EXPORTS = (
     "fft3d_batch_launch", "fft3d_batch_status", "fft3d_batch_describe", "fft3d_batch_destroy",
     "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
     "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy", "fft3d_r2c_transposed",
-    "fft3d_c2r_transposed",
+    "fft3d_c2r_transposed", "fft3d_r2c_pruned", "fft3d_c2r_pruned",
 )
 
 
@@ -123,6 +123,8 @@ def _load() -> ctypes.CDLL:
         "fft3d_server_destroy": (ctypes.c_int, [vp]),
         "fft3d_r2c_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fft3d_c2r_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fft3d_r2c_pruned": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(i64), vp]),
+        "fft3d_c2r_pruned": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -274,6 +276,23 @@ def fft3d_r2c_transposed(plan: Plan, x, Xt, work, stream=None) -> None:
 
 def fft3d_c2r_transposed(plan: Plan, Xt, y, work, stream=None) -> None:
     _check(lib.fft3d_c2r_transposed(plan.handle, _addr(Xt), _addr(y), _addr(work), _stream(stream)))
+
+
+def _kmax(kmax):
+    if kmax is None:
+        return None
+    k = [int(v) for v in kmax]
+    if len(k) != 3:
+        raise ValueError("kmax: three cuts (K0, K1, K2)")
+    return (ctypes.c_int64 * 3)(*k)
+
+
+def fft3d_r2c_pruned(plan: Plan, x, X, kmax, stream=None) -> None:
+    _check(lib.fft3d_r2c_pruned(plan.handle, _addr(x), _addr(X), _kmax(kmax), _stream(stream)))
+
+
+def fft3d_c2r_pruned(plan: Plan, X, y, kmax, work=None, stream=None) -> None:
+    _check(lib.fft3d_c2r_pruned(plan.handle, _addr(X), _addr(y), _addr(work), _kmax(kmax), _stream(stream)))
 
 
 def fft3d_batch_submit(items, stream=None) -> None:
@@ -498,6 +517,26 @@ def c2r(plan: Plan, X, y=None, work=None, stream=None):
         y = empty_real(plan, X.device)
     _shape_check(plan, y, X)
     fft3d_c2r(plan, X, y, work, stream)
+    return y
+
+
+def r2c_pruned(plan: Plan, x, kmax, X=None, stream=None):
+    """Pruned forward transform: X holds the kept modes of the box kmax (its
+    other elements are unspecified); X is allocated if None."""
+    if X is None:
+        X = empty_complex(plan, x.device)
+    _shape_check(plan, x, X)
+    fft3d_r2c_pruned(plan, x, X, kmax, stream)
+    return X
+
+
+def c2r_pruned(plan: Plan, X, kmax, y=None, work=None, stream=None):
+    """Pruned inverse transform: reads only the kept modes of X; X is
+    preserved iff work is given."""
+    if y is None:
+        y = empty_real(plan, X.device)
+    _shape_check(plan, y, X)
+    fft3d_c2r_pruned(plan, X, y, kmax, work, stream)
     return y
 
 

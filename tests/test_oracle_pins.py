@@ -358,3 +358,55 @@ def test_k53_field_spectrum_recovered(oracle):
     k2 = np.arange(21)[None, None, :]
     kk = np.sqrt(k0 ** 2 + k1 ** 2 + k2 ** 2)
     assert np.all(np.abs(X[kk > kmax]) < 1e-9 * np.abs(X).max())
+
+
+# ------------------------------------------------------------ pruned --
+
+@pytest.mark.parametrize("shape,kmax", [((12, 10, 16), (4, 3, 5)), ((9, 8, 6), (2, -1, 1)), ((8, 8, 8), (-1, -1, -1)),
+                                        ((6, 7, 10), (0, 0, 0))])
+def test_box_mask_counts(oracle, shape, kmax):
+    """Closed-form size of the box: (2K0+1)(2K1+1)(K2+1), a whole axis for K < 0."""
+    n0, n1, n2 = shape
+    K0, K1, K2 = kmax
+    want = (n0 if K0 < 0 else 2 * K0 + 1) * (n1 if K1 < 0 else 2 * K1 + 1) * (n2 // 2 + 1 if K2 < 0 else K2 + 1)
+    assert int(oracle.box_mask(shape, kmax).sum()) == want
+
+
+def test_pruned_pair_keeps_exactly_the_box_cosines(oracle):
+    """A field made of single cosines, some with wavevectors on the edge of
+    the box (kept) and some one step beyond it (dropped), including negative
+    k0/k1 and the k2 = 0 plane: the pruned inverse of the forward transform
+    is N times the sum of the kept cosines alone, evaluated directly."""
+    shape = (18, 16, 20)
+    n0, n1, n2 = shape
+    kmax = (5, 4, 6)
+    j0, j1, j2 = np.meshgrid(np.arange(n0), np.arange(n1), np.arange(n2), indexing="ij")
+    waves = [((5, -4, 6), True), ((-5, 4, 0), True), ((0, 0, 0), True), ((3, 1, 2), True),
+             ((6, 0, 1), False), ((0, -5, 3), False), ((1, 2, 7), False), ((-6, 4, 0), False)]
+    rng = np.random.default_rng(8)
+    x = np.zeros(shape)
+    kept = np.zeros(shape)
+    for (k0, k1, k2), inside in waves:
+        a, ph = 1.0 + rng.random(), 2 * np.pi * rng.random()
+        term = a * np.cos(2 * np.pi * (k0 * j0 / n0 + k1 * j1 / n1 + k2 * j2 / n2) + ph)
+        x += term
+        if inside:
+            kept += term
+    X = oracle.r2c_pruned(x, kmax)
+    y = oracle.c2r_pruned(X, n2, kmax) / x.size
+    assert rel(y, kept) < 1e-13
+    # c2r_pruned also ignores whatever sits outside the box
+    Xf = oracle.r2c(x)
+    assert rel(oracle.c2r_pruned(Xf, n2, kmax) / x.size, kept) < 1e-13
+
+
+def test_r2c_pruned_zero_outside_and_exact_inside(oracle):
+    shape = (10, 12, 14)
+    kmax = (3, 4, 5)
+    x = fields.uniform(shape, seed=9)
+    X = oracle.r2c_pruned(x, kmax)
+    for k in [(3, -4 % 12, 5), (-3 % 10, 4, 0), (0, 0, 0)]:
+        want = oracle.r2c_point(x, k)
+        assert abs(X[k] - want) <= 1e-12 * abs(want)
+    for k in [(4, 0, 0), (0, 5, 1), (0, 12 - 5, 2), (1, 1, 6), (10 - 4, 0, 3)]:
+        assert X[k] == 0
