@@ -111,16 +111,17 @@ template <typename T> struct PlaneColsMaskIO {
 // Column pass over the kept columns: block b of the pass starts at
 // (b < nb_lo ? b : b + nskip) * bstride (the two kept ranges of k1 for the
 // n0 pass; nskip = 0 for the n1 pass), ncols = K2 + 1 columns per block.
+// reverse: as in k_cols (each XCD walks its groups from the last).
 template <typename T, int NT, int EPT, bool INV>
 __global__ __launch_bounds__(NT) void k_cols_pr(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
                                                 const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
                                                 int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
                                                 int64_t ntiles, int64_t ngroups, int gsize, int64_t nb_lo,
-                                                int64_t nskip, int kin, int kout)
+                                                int64_t nskip, int kin, int kout, int reverse)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int64_t t = group_tile(blockIdx.x, ngroups, gsize, false);
+    const int64_t t = group_tile(blockIdx.x, ngroups, gsize, reverse);
     if (t >= ntiles) return;  // padding workgroup
     const int64_t b = t / tiles_per_batch;
     const int64_t c0 = (t - b * tiles_per_batch) * W;
@@ -178,11 +179,12 @@ __global__ __launch_bounds__(NT) void k_rows_r2c_pr(const T* x, cx<T>* X, const 
 }
 
 // Rows pass, inverse: as k_rows_c2r, reading bins 0 .. Hw-1 of each row only
-// (the others are zero).
+// (the others are zero).  mgHw = div_magic(Hw), mgZ = div_magic(H - Hw).
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_c2r_pr(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                     const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
-                                                    int64_t nrows, int rpw, int Hs, int Hw, uint32_t mgH)
+                                                    int64_t nrows, int rpw, int Hs, int Hw, uint32_t mgHw,
+                                                    uint32_t mgZ)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -192,11 +194,32 @@ __global__ __launch_bounds__(NT) void k_rows_c2r_pr(const cx<T>* X, T* y, const 
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
     const cx<T>* src = X + row0 * H;
-    const int count = rows * H;
-    for (int e = (int)threadIdx.x; e < count; e += NT) {
-        const int q = fdiv(e, mgH);
-        const int c = e - q * H;
-        buf[q * Hs + pad16(c)] = c < Hw ? src[(int64_t)q * H + c] : mk<T>((T)0, (T)0);
+    // kept bins: 8 loads in flight per thread before the LDS stores
+    constexpr int U = 8;
+    const int count = rows * Hw;
+    for (int base = 0; base < count; base += U * NT) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            const int ec = e < count ? e : count - 1;  // always a kept bin
+            const int q = fdiv(ec, mgHw);
+            v[u] = src[(int64_t)q * H + (ec - q * Hw)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + (int)threadIdx.x + u * NT;
+            if (e < count) {
+                const int q = fdiv(e, mgHw);
+                buf[q * Hs + pad16(e - q * Hw)] = v[u];
+            }
+        }
+    }
+    // the other bins are zero
+    const int nz = H - Hw, zcount = rows * nz;
+    for (int e = (int)threadIdx.x; e < zcount; e += NT) {
+        const int q = fdiv(e, mgZ);
+        buf[q * Hs + pad16(Hw + e - q * nz)] = mk<T>((T)0, (T)0);
     }
     __syncthreads();
     merge_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
@@ -316,7 +339,7 @@ template <typename T> hipError_t init_pruned()
 // of every plane.  kin / kout: row masks of the loads / stores.
 template <typename T, bool INV>
 hipError_t cols_pr_t(const Plan& p, const ColPass& cp0, int axis, int64_t tw_off, const void* in, void* out,
-                     const PrunedBox& b, int kin, int kout, hipStream_t st)
+                     const PrunedBox& b, int kin, int kout, int rev, hipStream_t st)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
     ColPass cp = cp0;
@@ -347,7 +370,7 @@ hipError_t cols_pr_t(const Plan& p, const ColPass& cp0, int axis, int64_t tw_off
 #define FFT3D_COLS_PR(NT_, EPT_)                                                                               \
     hipLaunchKernelGGL((k_cols_pr<T, NT_, EPT_, INV>), dim3(grid), dim3(NT_), cp.lds, st, ci, co, ax,            \
                        table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W, mgw, cp.tiles_per_batch, ntiles, \
-                       ngroups, gsize, nb_lo, nskip, kin, kout)
+                       ngroups, gsize, nb_lo, nskip, kin, kout, rev)
     if (cp.big) FFT3D_COLS_PR(kNtBig, EB);
     else if (cp.wide) FFT3D_COLS_PR(kNtWide, ES);
     else FFT3D_COLS_PR(kNtSmall, ES);
@@ -377,15 +400,15 @@ hipError_t rows_pr_t(const Plan& p, const void* in, void* out, bool inverse, con
     } else {
         const cx<T>* Xi = static_cast<const cx<T>*>(in);
         T* yo = static_cast<T*>(out);
-        const uint32_t mg = div_magic((uint32_t)p.H);
+        const uint32_t mg = div_magic((uint32_t)Hw), mgz = div_magic((uint32_t)(p.H - Hw));
         if (p.rows_big)
             hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
                                dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs,
-                               Hw, mg);
+                               Hw, mg, mgz);
         else
             hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
                                yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw,
-                               p.Hs, Hw, mg);
+                               p.Hs, Hw, mg, mgz);
     }
     return hipGetLastError();
 }
@@ -421,9 +444,9 @@ template <typename T> hipError_t pruned_r2c_t(const Plan& p, const void* x, void
         e = plane_pr_t<T>(p, x, X, false, b, st);
     } else {
         e = rows_pr_t<T>(p, x, X, false, b, st);
-        if (e == hipSuccess && p.n1 > 1) e = cols_pr_t<T, false>(p, p.pass1, 1, p.off_ax1, X, X, b, -1, b.K1, st);
+        if (e == hipSuccess && p.n1 > 1) e = cols_pr_t<T, false>(p, p.pass1, 1, p.off_ax1, X, X, b, -1, b.K1, 1, st);
     }
-    if (e == hipSuccess && p.n0 > 1) e = cols_pr_t<T, false>(p, p.pass0, 0, p.off_ax0, X, X, b, -1, b.K0, st);
+    if (e == hipSuccess && p.n0 > 1) e = cols_pr_t<T, false>(p, p.pass0, 0, p.off_ax0, X, X, b, -1, b.K0, 0, st);
     return e;
 }
 
@@ -436,13 +459,13 @@ hipError_t pruned_c2r_t(const Plan& p, const void* X, void* y, void* work, const
     void* scratch = work ? work : const_cast<void*>(X);
     const void* cur = X;
     if (p.n0 > 1) {
-        e = cols_pr_t<T, true>(p, p.pass0, 0, p.off_ax0, cur, scratch, b, b.K0, -1, st);
+        e = cols_pr_t<T, true>(p, p.pass0, 0, p.off_ax0, cur, scratch, b, b.K0, -1, 0, st);
         cur = scratch;
     }
     if (e != hipSuccess) return e;
     if (p.fused_plane) return plane_pr_t<T>(p, cur, y, true, b, st);
     if (p.n1 > 1) {
-        e = cols_pr_t<T, true>(p, p.pass1, 1, p.off_ax1, cur, scratch, b, b.K1, -1, st);
+        e = cols_pr_t<T, true>(p, p.pass1, 1, p.off_ax1, cur, scratch, b, b.K1, -1, 1, st);
         cur = scratch;
     }
     if (e == hipSuccess) e = rows_pr_t<T>(p, cur, y, true, b, st);
