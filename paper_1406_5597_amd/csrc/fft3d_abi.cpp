@@ -150,18 +150,18 @@ int enqueue_r2c(const fft3d::Plan& p, const void* x, void* X, hipStream_t s)
             const int64_t gn = std::min(G, p.n0 - g0);
             const char* xg = static_cast<const char*>(x) + g0 * p.n1 * p.n2 * p.elem;
             char* Xg = static_cast<char*>(X) + g0 * p.n1 * p.H * 2 * p.elem;
-            e = fft3d::launch_rows_r2c(p, xg, Xg, gn * p.n1, 0, s);
+            e = fft3d::launch_rows_r2c(p, xg, Xg, gn * p.n1, p.rev & 1, s);
             if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
             if (p.n1 > 1) {
                 fft3d::ColPass cp = p.pass1;
                 cp.nbatch = gn;
-                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, Xg, Xg, false, 1, s);
+                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, Xg, Xg, false, (p.rev >> 1) & 1, s);
                 if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
             }
         }
     }
     if (p.n0 > 1) {
-        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, X, X, false, 0, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, X, X, false, (p.rev >> 2) & 1, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n0 columns kernel");
     }
     return FFT3D_OK;
@@ -175,7 +175,7 @@ int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t 
     void* scratch = work ? work : X;
     const void* cur = X;
     if (p.n0 > 1) {
-        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, cur, scratch, true, 0, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, cur, scratch, true, (p.rev >> 3) & 1, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n0 columns kernel");
         cur = scratch;
     }
@@ -202,12 +202,12 @@ int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t 
                 fft3d::ColPass cp = p.pass1;
                 cp.nbatch = gn;
                 void* dst = static_cast<char*>(scratch) + off;
-                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, src, dst, true, 1, s);
+                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, src, dst, true, (p.rev >> 4) & 1, s);
                 if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
                 src = dst;
             }
             char* yg = static_cast<char*>(y) + g0 * p.n1 * p.n2 * p.elem;
-            e = fft3d::launch_rows_c2r(p, src, yg, gn * p.n1, 0, s);
+            e = fft3d::launch_rows_c2r(p, src, yg, gn * p.n1, (p.rev >> 5) & 1, s);
             if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
         }
     }
@@ -725,14 +725,14 @@ int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStrea
         if (overlaps(in, rb, out, cb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
         e = p.fused_plane ? fft3d::launch_plane_r2c(p, in, out, s)
             : p.coop      ? fft3d::launch_plane_coop(p, in, out, false, s)
-                          : fft3d::launch_rows_r2c(p, in, out, p.n0 * p.n1, 0, s);
+                          : fft3d::launch_rows_r2c(p, in, out, p.n0 * p.n1, p.rev & 1, s);
         break;
     case FFT3D_PASS_PLANE_C2R:
         // the cooperative plane c2r transforms the n1 columns of `in` in place
         if (overlaps(in, cb, out, rb)) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out overlap");
         e = p.fused_plane ? fft3d::launch_plane_c2r(p, in, out, s)
             : p.coop      ? fft3d::launch_plane_coop(p, in, out, true, s)
-                          : fft3d::launch_rows_c2r(p, in, out, p.n0 * p.n1, 0, s);
+                          : fft3d::launch_rows_c2r(p, in, out, p.n0 * p.n1, (p.rev >> 5) & 1, s);
         break;
     case FFT3D_PASS_N1_FWD:
     case FFT3D_PASS_N1_INV:
@@ -740,14 +740,16 @@ int fft3d_run_pass(fft3d_plan_t h, int pass, const void* in, void* out, hipStrea
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n1 pass");
         if (in != out && overlaps(in, cb, out, cb))
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
-        e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, in, out, pass == FFT3D_PASS_N1_INV, 1, s);
+        e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, in, out, pass == FFT3D_PASS_N1_INV,
+                               pass == FFT3D_PASS_N1_INV ? (p.rev >> 4) & 1 : (p.rev >> 1) & 1, s);
         break;
     case FFT3D_PASS_N0_FWD:
     case FFT3D_PASS_N0_INV:
         if (p.n0 == 1) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: plan has no n0 pass");
         if (in != out && overlaps(in, cb, out, cb))
             return fail(FFT3D_ERR_INVALID_ARG, "fft3d_run_pass: in and out partially overlap");
-        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV, 0, s);
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, in, out, pass == FFT3D_PASS_N0_INV,
+                               pass == FFT3D_PASS_N0_INV ? (p.rev >> 3) & 1 : (p.rev >> 2) & 1, s);
         break;
     case FFT3D_PASS_SWAP01:
     case FFT3D_PASS_SWAP10:

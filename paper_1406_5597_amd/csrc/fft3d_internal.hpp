@@ -93,6 +93,11 @@ struct Plan {
     int coop_lag = 2;              // slots between a plane's two phases
     int64_t plane_group = 0;       // split plane step in groups of this many planes (0: all at once)
     int n0_group = 1;              // n0-pass tiles sent together to one XCD (see plan_build_host)
+    // Passes that walk their tiles in reverse (each XCD from its last group),
+    // one bit per pass: 1 rows r2c, 2 n1 forward, 4 n0 forward, 8 n0 inverse,
+    // 16 n1 inverse, 32 rows c2r.  A pass that reads what the previous pass
+    // wrote last first finds more of it still in the memory-side cache.
+    int rev = 2 | 16;
     int64_t coop_ctr_count = 0;
     int* d_ctr = nullptr;
     AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h

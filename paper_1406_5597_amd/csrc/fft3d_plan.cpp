@@ -369,6 +369,8 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     // (FP64) of them on one XCD measured 1.5-3% faster pairs at 512^3
     p.n0_group = dtype == FFT3D_F64 ? 16 : 8;
     if (const char* g = getenv("FFT3D_N0_GROUP")) p.n0_group = std::max(1, atoi(g));
+    // walk order of each pass (tuning override, bits as Plan::rev)
+    if (const char* r = getenv("FFT3D_REV")) p.rev = atoi(r) & 63;
     // tuning override of the n0 tile width (power of two; ignored if it does
     // not fit a tier)
     if (const char* w = getenv("FFT3D_N0_W")) {
@@ -442,7 +444,7 @@ std::string Plan::describe() const
         }
         r += "\"n1_pass\": " + pass_json(pass1) + "}, ";
     }
-    r += "\"n0_pass\": " + pass_json(pass0) + ", \"n0_group\": " + std::to_string(n0_group) + ", ";
+    r += "\"n0_pass\": " + pass_json(pass0) + ", \"n0_group\": " + std::to_string(n0_group) + ", \"rev\": " + std::to_string(rev) + ", ";
     // pass lists (FFT3D_PASS_* ids) of the two directions
     std::string f = "[0", i = "[";
     const bool n1_pass = !fused_plane && !coop && n1 > 1;

@@ -444,9 +444,9 @@ template <typename T> hipError_t pruned_r2c_t(const Plan& p, const void* x, void
         e = plane_pr_t<T>(p, x, X, false, b, st);
     } else {
         e = rows_pr_t<T>(p, x, X, false, b, st);
-        if (e == hipSuccess && p.n1 > 1) e = cols_pr_t<T, false>(p, p.pass1, 1, p.off_ax1, X, X, b, -1, b.K1, 1, st);
+        if (e == hipSuccess && p.n1 > 1) e = cols_pr_t<T, false>(p, p.pass1, 1, p.off_ax1, X, X, b, -1, b.K1, (p.rev >> 1) & 1, st);
     }
-    if (e == hipSuccess && p.n0 > 1) e = cols_pr_t<T, false>(p, p.pass0, 0, p.off_ax0, X, X, b, -1, b.K0, 0, st);
+    if (e == hipSuccess && p.n0 > 1) e = cols_pr_t<T, false>(p, p.pass0, 0, p.off_ax0, X, X, b, -1, b.K0, (p.rev >> 2) & 1, st);
     return e;
 }
 
@@ -459,13 +459,13 @@ hipError_t pruned_c2r_t(const Plan& p, const void* X, void* y, void* work, const
     void* scratch = work ? work : const_cast<void*>(X);
     const void* cur = X;
     if (p.n0 > 1) {
-        e = cols_pr_t<T, true>(p, p.pass0, 0, p.off_ax0, cur, scratch, b, b.K0, -1, 0, st);
+        e = cols_pr_t<T, true>(p, p.pass0, 0, p.off_ax0, cur, scratch, b, b.K0, -1, (p.rev >> 3) & 1, st);
         cur = scratch;
     }
     if (e != hipSuccess) return e;
     if (p.fused_plane) return plane_pr_t<T>(p, cur, y, true, b, st);
     if (p.n1 > 1) {
-        e = cols_pr_t<T, true>(p, p.pass1, 1, p.off_ax1, cur, scratch, b, b.K1, -1, 1, st);
+        e = cols_pr_t<T, true>(p, p.pass1, 1, p.off_ax1, cur, scratch, b, b.K1, -1, (p.rev >> 4) & 1, st);
         cur = scratch;
     }
     if (e == hipSuccess) e = rows_pr_t<T>(p, cur, y, true, b, st);
