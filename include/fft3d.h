@@ -95,7 +95,7 @@ enum {
 int fft3d_version(void);
 
 /* Create a plan for an n0 x n1 x n2 real array in the given dtype.
- * Supported extents: every n >= 1 whose prime factors are 2 and 3, with
+ * Supported extents: every n >= 1 whose prime factors are 2, 3, 5 and 7, with
  * n0, n1 <= 4096, n2 even and n2 <= 8192.  Other extents return
  * FFT3D_ERR_UNSUPPORTED; n < 1, a bad dtype or out == NULL return
  * FFT3D_ERR_INVALID_ARG.  Builds the radix schedules and the twiddle table
@@ -162,7 +162,9 @@ typedef struct {
  * No allocation: the task list is staged through a ring of pinned/device
  * buffers set up when the first plan on the device was created (8 launches
  * deep; a submit that finds its ring slot still in flight waits for it).
- * Batches of more than 4096 passes are split into several launches. */
+ * Batches of more than 4096 passes are split into several launches.
+ * Items whose extents have a factor 5 or 7 run their own kernels (as
+ * fft3d_r2c / fft3d_c2r), on the same stream after the batched launch. */
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream);
 
 /* flags of fft3d_batch_submit_ex / fft3d_batch_create */
@@ -178,6 +180,10 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
  * and the launch is a hipGraph of one kernel node (instantiated here) unless
  * FFT3D_BATCH_DIRECT.  The item pointers are fixed at creation.  The same
  * concurrency rules as fft3d_batch_submit apply; at most 4096 passes.
+ * Items whose extents have a factor 5 or 7 are refused here
+ * (FFT3D_ERR_UNSUPPORTED): the batched kernel has only the radix-2/3 stages;
+ * fft3d_batch_submit runs such items with their own kernels, after the
+ * batched launch of the others.
  * Launches of one handle must not overlap in time (same stream, or ordered);
  * the kernel leaves its counters cleared for the next launch. */
 typedef struct fft3d_batch_s* fft3d_batch_t;

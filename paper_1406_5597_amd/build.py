@@ -36,6 +36,10 @@ SOURCES = [
     ("fft3d_batch.hip", DEVICE_FLAGS),
     ("fft3d_pruned_f32.hip", DEVICE_FLAGS),
     ("fft3d_pruned_f64.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f32_odd.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f64_odd.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f32_odd.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f64_odd.hip", DEVICE_FLAGS),
     ("fft3d_batch_host.cpp", HOST_FLAGS),
     ("fft3d_server.cpp", HOST_FLAGS),
     ("fft3d_plan.cpp", HOST_FLAGS),

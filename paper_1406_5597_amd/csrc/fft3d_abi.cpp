@@ -570,17 +570,27 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
         return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": unknown flags");
     int rc = validate_batch(items, n, who);
     if (rc || n == 0) return rc;
+    auto run_alone = [&](const fft3d_batch_item& it) {
+        if (it.dir == FFT3D_R2C) return enqueue_r2c(it.plan->p, it.in, it.out, s);
+        if (it.dir == FFT3D_C2R) return enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
+        int r = enqueue_r2c(it.plan->p, it.in, it.mid, s);
+        return r ? r : enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
+    };
     if (flags & FFT3D_BATCH_SEQUENTIAL) {
-        for (int i = 0; i < n; ++i) {
-            const fft3d_batch_item& it = items[i];
-            if (it.dir == FFT3D_R2C) rc = enqueue_r2c(it.plan->p, it.in, it.out, s);
-            else if (it.dir == FFT3D_C2R) rc = enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
-            else {
-                rc = enqueue_r2c(it.plan->p, it.in, it.mid, s);
-                if (!rc) rc = enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
-            }
-            if (rc) return rc;
-        }
+        for (int i = 0; i < n; ++i)
+            if ((rc = run_alone(items[i]))) return rc;
+        return FFT3D_OK;
+    }
+    // items with radix-5/7 extents run their own kernels, after the batched
+    // launch of the others (the batched kernel has only the 2/3 stages)
+    std::vector<fft3d_batch_item> even;
+    even.reserve(n);
+    for (int i = 0; i < n; ++i)
+        if (!items[i].plan->p.odd) even.push_back(items[i]);
+    if ((int)even.size() < n) {
+        if (!even.empty() && (rc = fft3d_batch_submit_ex(even.data(), (int)even.size(), 0, s))) return rc;
+        for (int i = 0; i < n; ++i)
+            if (items[i].plan->p.odd && (rc = run_alone(items[i]))) return rc;
         return FFT3D_OK;
     }
     fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
@@ -610,6 +620,10 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
     if (n < 1) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": empty batch");
     int rc = validate_batch(items, n, who);
     if (rc) return rc;
+    for (int i = 0; i < n; ++i)
+        if (items[i].plan->p.odd)
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": item " + std::to_string(i) +
+                                                   " has radix-5/7 extents (use fft3d_batch_submit)");
     fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
     std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
     if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");

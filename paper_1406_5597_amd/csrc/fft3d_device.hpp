@@ -2,7 +2,7 @@
 //
 // Complex arithmetic with explicit fused multiply-adds (the library is built
 // with -ffp-contract=off, so the rounding of every expression is fixed by the
-// source and identical in every kernel that inlines it), the radix-2/3/4/8/16
+// source and identical in every kernel that inlines it), the radix-2/3/4/5/7/8/16
 // DFT butterflies held in registers, and a Stockham autosort stage that runs on
 // lines held in LDS.
 //
@@ -20,7 +20,22 @@
 
 #include "fft3d_sched.hpp"
 
+// Radix-5 and radix-7 stages are compiled into the kernels only when
+// FFT3D_ODD_RADICES is 1: their extra cases in the stage dispatch raise the
+// register count of every kernel, so 2^a 3^b extents keep kernels without
+// them.  The two builds live in different inline namespaces, so both sets of
+// kernels link into one library.
+#ifndef FFT3D_ODD_RADICES
+#define FFT3D_ODD_RADICES 0
+#endif
+#if FFT3D_ODD_RADICES
+#define FFT3D_KNS k2357
+#else
+#define FFT3D_KNS k23
+#endif
+
 namespace fft3d {
+inline namespace FFT3D_KNS {
 
 template <typename T> struct cx_of;
 template <> struct cx_of<float> { using type = float2; };
@@ -167,10 +182,73 @@ template <bool INV, typename T> __device__ __forceinline__ void dft16(cx<T>* v)
     }
 }
 
+// cos and sin of 2 pi m / P for the odd radices 5 and 7, m in [0, P).
+template <int P> __device__ __forceinline__ constexpr long double cos_2pi(int m)
+{
+    const int r = m <= P / 2 ? m : P - m;  // cos is even about P/2
+    if constexpr (P == 5) {
+        return r == 0 ? 1.0L : r == 1 ? 0.309016994374947424102293417182819059L : -0.809016994374947424102293417182819059L;
+    } else {
+        return r == 0 ? 1.0L
+             : r == 1 ? 0.623489801858733530525004884004239811L
+             : r == 2 ? -0.222520933956314404288902564496794759L
+                      : -0.900968867902419126236102319507445051L;
+    }
+}
+template <int P> __device__ __forceinline__ constexpr long double sin_2pi(int m)
+{
+    const int r = m <= P / 2 ? m : P - m;  // sin is odd about P/2
+    const long double v = P == 5 ? (r == 0   ? 0.0L
+                                    : r == 1 ? 0.951056516295153572116439333379382143L
+                                             : 0.587785252292473129168705954639072769L)
+                                 : (r == 0   ? 0.0L
+                                    : r == 1 ? 0.781831482468029808708444526674057750L
+                                    : r == 2 ? 0.974927912181823607018131682993931217L
+                                             : 0.433883739117558120475768332848358755L);
+    return m <= P / 2 ? v : -v;
+}
+
+// Length-P DFT for odd P (5, 7) by the symmetric pairs of inputs:
+// a_j = x_j + x_{P-j}, b_j = x_j - x_{P-j} (j = 1 .. (P-1)/2);
+// X_k = x_0 + sum_j a_j cos(2 pi jk/P) -/+ i sum_j b_j sin(2 pi jk/P), and
+// X_{P-k} the same with the opposite sign of the sine part (forward: minus
+// for X_k).
+template <int P, bool INV, typename T> __device__ __forceinline__ void dft_odd(cx<T>* v)
+{
+    constexpr int Hh = (P - 1) / 2;
+    cx<T> a[Hh + 1], b[Hh + 1];
+#pragma unroll
+    for (int j = 1; j <= Hh; ++j) {
+        a[j] = cadd<T>(v[j], v[P - j]);
+        b[j] = csub<T>(v[j], v[P - j]);
+    }
+    const cx<T> x0 = v[0];
+    cx<T> s0 = x0;
+#pragma unroll
+    for (int j = 1; j <= Hh; ++j) s0 = cadd<T>(s0, a[j]);
+#pragma unroll
+    for (int k = 1; k <= Hh; ++k) {
+        cx<T> A = x0, B = mk<T>((T)0, (T)0);
+#pragma unroll
+        for (int j = 1; j <= Hh; ++j) {
+            const int m = (j * k) % P;
+            const T c = (T)cos_2pi<P>(m), sn = (T)sin_2pi<P>(m);
+            A = mk<T>(fmaT(a[j].x, c, A.x), fmaT(a[j].y, c, A.y));
+            B = mk<T>(fmaT(b[j].x, sn, B.x), fmaT(b[j].y, sn, B.y));
+        }
+        // forward: X_k = A - i B, X_{P-k} = A + i B; inverse the reverse
+        const cx<T> miB = mk<T>(B.y, -B.x);
+        v[k] = INV ? csub<T>(A, miB) : cadd<T>(A, miB);
+        v[P - k] = INV ? cadd<T>(A, miB) : csub<T>(A, miB);
+    }
+    v[0] = s0;
+}
+
 template <int R, bool INV, typename T> __device__ __forceinline__ void dftR(cx<T>* v)
 {
     if constexpr (R == 2) dft2<INV, T>(v);
     else if constexpr (R == 3) dft3<INV, T>(v);
+    else if constexpr (R == 5 || R == 7) dft_odd<R, INV, T>(v);
     else if constexpr (R == 4) dft4<INV, T>(v);
     else if constexpr (R == 8) dft8<INV, T>(v);
     else if constexpr (R == 16) dft16<INV, T>(v);
@@ -506,6 +584,10 @@ __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines,
     case 8: stage<8, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     case 4: stage<4, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     case 3: stage<3, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+#if FFT3D_ODD_RADICES
+    case 5: stage<5, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    case 7: stage<7, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+#endif
     default: stage<2, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     }
 }
@@ -608,4 +690,5 @@ __device__ __forceinline__ void merge_rows(cx<T>* buf, int rows, int Hs, int h, 
     __syncthreads();
 }
 
+}  // inline namespace FFT3D_KNS
 }  // namespace fft3d

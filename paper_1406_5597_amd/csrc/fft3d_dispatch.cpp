@@ -5,6 +5,12 @@
 
 namespace fft3d {
 
+// The entry point of the plan's dtype, from the build with radix-5/7 stages
+// when the plan has them.
+#define FFT3D_PICK(p, name, ...)                                                                   \
+    ((p).dtype ? ((p).odd ? name##_f64_odd(__VA_ARGS__) : name##_f64(__VA_ARGS__))                 \
+               : ((p).odd ? name##_f32_odd(__VA_ARGS__) : name##_f32(__VA_ARGS__)))
+
 hipError_t coop_setup(Plan& p)
 {
     if (!p.coop) return hipSuccess;
@@ -37,6 +43,10 @@ hipError_t kernels_init()
     (void)init_coop_f64();
     (void)init_pruned_f32();
     (void)init_pruned_f64();
+    (void)init_plain_f32_odd();
+    (void)init_plain_f64_odd();
+    (void)init_pruned_f32_odd();
+    (void)init_pruned_f64_odd();
     (void)init_batch();
     (void)hipGetLastError();
     return hipSuccess;
@@ -48,38 +58,37 @@ hipError_t launch_plane_coop(const Plan& p, const void* in, void* out, bool inve
 }
 hipError_t launch_swap01(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t st)
 {
-    return p.dtype ? launch_swap01_f64(p, in, out, na, nb, st) : launch_swap01_f32(p, in, out, na, nb, st);
+    return FFT3D_PICK(p, launch_swap01, p, in, out, na, nb, st);
 }
 hipError_t launch_pruned_r2c(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t st)
 {
-    return p.dtype ? launch_pruned_r2c_f64(p, x, X, b, st) : launch_pruned_r2c_f32(p, x, X, b, st);
+    return FFT3D_PICK(p, launch_pruned_r2c, p, x, X, b, st);
 }
 hipError_t launch_pruned_c2r(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,
                              hipStream_t st)
 {
-    return p.dtype ? launch_pruned_c2r_f64(p, X, y, work, b, st) : launch_pruned_c2r_f32(p, X, y, work, b, st);
+    return FFT3D_PICK(p, launch_pruned_c2r, p, X, y, work, b, st);
 }
 hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st)
 {
-    return p.dtype ? launch_plane_r2c_f64(p, x, X, st) : launch_plane_r2c_f32(p, x, X, st);
+    return FFT3D_PICK(p, launch_plane_r2c, p, x, X, st);
 }
 hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t st)
 {
-    return p.dtype ? launch_plane_c2r_f64(p, X, y, st) : launch_plane_c2r_f32(p, X, y, st);
+    return FFT3D_PICK(p, launch_plane_c2r, p, X, y, st);
 }
 hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st)
 {
-    return p.dtype ? launch_rows_r2c_f64(p, x, X, nrows, rev, st) : launch_rows_r2c_f32(p, x, X, nrows, rev, st);
+    return FFT3D_PICK(p, launch_rows_r2c, p, x, X, nrows, rev, st);
 }
 hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st)
 {
-    return p.dtype ? launch_rows_c2r_f64(p, X, y, nrows, rev, st) : launch_rows_c2r_f32(p, X, y, nrows, rev, st);
+    return FFT3D_PICK(p, launch_rows_c2r, p, X, y, nrows, rev, st);
 }
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t st)
 {
-    return p.dtype ? launch_cols_f64(p, cp, axis, tw_off, in, out, inverse, rev, st)
-                   : launch_cols_f32(p, cp, axis, tw_off, in, out, inverse, rev, st);
+    return FFT3D_PICK(p, launch_cols, p, cp, axis, tw_off, in, out, inverse, rev, st);
 }
 
 }  // namespace fft3d

@@ -63,6 +63,7 @@ struct Plan {
     int64_t M = 0;            // n0*n1*H complex outputs
     int64_t N = 0;            // n0*n1*n2 real inputs
     int dtype = 0;            // 0 FP32, 1 FP64
+    bool odd = false;         // a schedule has radix-5/7 stages: the kernels built with them
     int elem = 4;             // bytes per real scalar
 
     AxisSched ax0{}, ax1{}, ax2h{};  // stage schedules: n0, n1, and h = n2/2
@@ -123,7 +124,7 @@ const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_l
 // tier.  False if not even one column does.
 bool small_colpass(const Plan& p, int axis, ColPass& cp);
 
-// Factor n = 2^a 3^b into stages; false if n has another prime factor.
+// Factor n = 2^a 3^b 5^c 7^d into stages; false if n has another prime factor.
 bool make_schedule(int64_t n, AxisSched& s);
 
 // e^{-2 pi i e/m}, quadrant-reduced, in long double.
@@ -160,6 +161,10 @@ struct PrunedBox {
                                        hipStream_t s);
 FFT3D_DECLARE_DTYPE(f32)
 FFT3D_DECLARE_DTYPE(f64)
+// the builds with radix-5/7 stages (fft3d_kern_*_odd.hip, fft3d_pruned_*_odd.hip;
+// no cooperative kernel)
+FFT3D_DECLARE_DTYPE(f32_odd)
+FFT3D_DECLARE_DTYPE(f64_odd)
 #undef FFT3D_DECLARE_DTYPE
 
 // Launchers (enqueue on `stream`, no allocation, no synchronisation).

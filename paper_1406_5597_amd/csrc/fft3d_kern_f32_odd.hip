@@ -1,0 +1,4 @@
+// fft3d_kern_f32_odd.hip -- the standalone kernels with the radix-5 and radix-7 stages
+// compiled in, for plans whose extents have those factors.
+#define FFT3D_ODD_RADICES 1
+#include "fft3d_kern_f32.hip"

@@ -23,6 +23,7 @@
 #include "fft3d_internal.hpp"
 
 namespace fft3d {
+inline namespace FFT3D_KNS {
 
 // ------------------------------------------------------------- kernels --
 
@@ -802,4 +803,5 @@ template <typename T> hipError_t coop_occupancy(const Plan& p, int* per_cu)
 }
 
 
+}  // inline namespace FFT3D_KNS
 }  // namespace fft3d

@@ -14,9 +14,9 @@ namespace fft3d {
 
 // ------------------------------------------------------------ schedules --
 
-// n = 2^a 3^b.  The power-of-two part takes ceil(a/4) stages with radices as
-// equal as possible (512 = 8*8*8, 1024 = 16*8*8, 256 = 16*16, 32 = 8*4),
-// followed by one radix-3 stage per factor 3.
+// n = 2^a 3^b 5^c 7^d.  The power-of-two part takes ceil(a/4) stages with
+// radices as equal as possible (512 = 8*8*8, 1024 = 16*8*8, 256 = 16*16,
+// 32 = 8*4), followed by one radix-3, -5 or -7 stage per odd factor.
 bool make_schedule(int64_t n, AxisSched& s)
 {
     s = AxisSched{};
@@ -32,6 +32,15 @@ bool make_schedule(int64_t n, AxisSched& s)
         m /= 3;
         ++b;
     }
+    int c5 = 0, c7 = 0;
+    while (m % 5 == 0) {
+        m /= 5;
+        ++c5;
+    }
+    while (m % 7 == 0) {
+        m /= 7;
+        ++c7;
+    }
     if (m != 1) return false;
     int radices[kMaxStages];
     int cnt = 0;
@@ -46,6 +55,14 @@ bool make_schedule(int64_t n, AxisSched& s)
     for (int i = 0; i < b; ++i) {
         if (cnt >= kMaxStages) return false;
         radices[cnt++] = 3;
+    }
+    for (int i = 0; i < c5; ++i) {
+        if (cnt >= kMaxStages) return false;
+        radices[cnt++] = 5;
+    }
+    for (int i = 0; i < c7; ++i) {
+        if (cnt >= kMaxStages) return false;
+        radices[cnt++] = 7;
     }
     int32_t ns = 1, off = 0;
     for (int i = 0; i < cnt; ++i) {
@@ -253,11 +270,15 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     p.dtype = dtype;
     p.elem = dtype == FFT3D_F64 ? 8 : 4;
     if (!make_schedule(n0, p.ax0) || !make_schedule(n1, p.ax1) || !make_schedule(p.h, p.ax2h)) {
-        snprintf(msg, sizeof msg, "extents %lld x %lld x %lld: n0, n1 and n2/2 must have no prime factor other than 2 and 3",
+        snprintf(msg, sizeof msg, "extents %lld x %lld x %lld: n0, n1 and n2/2 must have no prime factor other than 2, 3, 5 and 7",
                  (long long)n0, (long long)n1, (long long)n2);
         why = msg;
         return FFT3D_ERR_UNSUPPORTED;
     }
+
+    for (const AxisSched* a : {&p.ax0, &p.ax1, &p.ax2h})
+        for (int i = 0; i < a->nst; ++i)
+            if (a->radix[i] == 5 || a->radix[i] == 7) p.odd = true;
 
     // twiddle table: [n2/2 stages | split roots k = 0..h | n1 stages | n0 stages]
     p.off_ax2h = 0;
@@ -332,7 +353,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         }
         // one cooperative launch for the plane step when both task kinds fit
         // the small tier (and the caller did not ask for the two-kernel path)
-        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1) {
+        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1 && !p.odd) {
             p.coop = true;
             p.coop_rpw = p.rpw;
             p.coop_w = p.pass1.W;
@@ -444,7 +465,7 @@ std::string Plan::describe() const
         }
         r += "\"n1_pass\": " + pass_json(pass1) + "}, ";
     }
-    r += "\"n0_pass\": " + pass_json(pass0) + ", \"n0_group\": " + std::to_string(n0_group) + ", \"rev\": " + std::to_string(rev) + ", ";
+    r += "\"n0_pass\": " + pass_json(pass0) + ", \"n0_group\": " + std::to_string(n0_group) + ", \"rev\": " + std::to_string(rev) + ", \"radix57\": " + (odd ? "true" : "false") + ", ";
     // pass lists (FFT3D_PASS_* ids) of the two directions
     std::string f = "[0", i = "[";
     const bool n1_pass = !fused_plane && !coop && n1 > 1;

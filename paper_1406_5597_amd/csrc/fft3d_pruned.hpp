@@ -18,6 +18,7 @@
 #include "fft3d_kernels.hpp"
 
 namespace fft3d {
+inline namespace FFT3D_KNS {
 
 // Kept index along an axis of length n with cut K: |signed index| <= K.
 // K < 0 keeps everything.
@@ -472,4 +473,5 @@ hipError_t pruned_c2r_t(const Plan& p, const void* X, void* y, void* work, const
     return e;
 }
 
+}  // inline namespace FFT3D_KNS
 }  // namespace fft3d

@@ -2,14 +2,21 @@
 // see fft3d_pruned.hpp.
 #include "fft3d_pruned.hpp"
 
+// entry points of this build: name_f64, or name_f64_odd with the radix-5/7 stages
+#if FFT3D_ODD_RADICES
+#define FFT3D_ENTRY(name) name##_f64_odd
+#else
+#define FFT3D_ENTRY(name) name##_f64
+#endif
+
 namespace fft3d {
 
-hipError_t init_pruned_f64() { return init_pruned<double>(); }
-hipError_t launch_pruned_r2c_f64(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t s)
+hipError_t FFT3D_ENTRY(init_pruned)() { return init_pruned<double>(); }
+hipError_t FFT3D_ENTRY(launch_pruned_r2c)(const Plan& p, const void* x, void* X, const PrunedBox& b, hipStream_t s)
 {
     return pruned_r2c_t<double>(p, x, X, b, s);
 }
-hipError_t launch_pruned_c2r_f64(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,
+hipError_t FFT3D_ENTRY(launch_pruned_c2r)(const Plan& p, const void* X, void* y, void* work, const PrunedBox& b,
                                    hipStream_t s)
 {
     return pruned_c2r_t<double>(p, X, y, work, b, s);

@@ -46,7 +46,7 @@ def test_binding_has_no_fallback():
 
 @pytest.mark.parametrize("shape,dtype,code", [
     ((0, 4, 4), "f32", -1), ((4, -1, 4), "f64", -1), ((4, 4, 0), "f32", -1),
-    ((5, 4, 4), "f32", -2), ((4, 7, 4), "f64", -2), ((4, 4, 10), "f32", -2),
+    ((11, 4, 4), "f32", -2), ((4, 13, 4), "f64", -2), ((4, 4, 22), "f32", -2),
     ((4, 4, 5), "f32", -2), ((4, 4, 7), "f64", -2), ((8192, 4, 4), "f32", -2),
     ((4, 4, 16384), "f32", -2),
 ])
@@ -93,19 +93,30 @@ def test_batch_submit_all_or_nothing(F):
         F.fft3d_batch_submit([(p, 9, 256, 0, 4096, 0)], stream=0)
 
 
-def smooth23(limit):
-    return sorted(2 ** a * 3 ** b for a in range(13) for b in range(8) if 2 ** a * 3 ** b <= limit)
+def smooth2357(limit):
+    out = set()
+    for a in range(13):
+        for b in range(8):
+            for c in range(6):
+                for d in range(5):
+                    n = 2 ** a * 3 ** b * 5 ** c * 7 ** d
+                    if n <= limit:
+                        out.add(n)
+    return sorted(out)
 
 
 def test_schedules_factor_every_length(F):
-    for n in smooth23(4096):
+    for n in smooth2357(4096):
         p = F.Plan(n, 1, 2, "f32", host_only=True)
         rad = p.describe()["schedules"]["n0"]["radices"]
         assert int(np.prod(rad)) == n if n > 1 else rad == []
-        assert all(r in (2, 3, 4, 8, 16) for r in rad)
+        assert all(r in (2, 3, 4, 5, 7, 8, 16) for r in rad)
         # the power-of-two part takes the fewest stages of radix <= 16
         a = (n & -n).bit_length() - 1
-        assert sum(1 for r in rad if r != 3) == (a + 3) // 4
+        assert sum(1 for r in rad if r not in (3, 5, 7)) == (a + 3) // 4
+    for n in (11, 13, 22, 4097 * 2):
+        with pytest.raises(F.Fft3dError):
+            F.Plan(n, 1, 2, "f32", host_only=True)
 
 
 _PI50 = None
