@@ -96,7 +96,7 @@ int fft3d_version(void);
 
 /* Create a plan for an n0 x n1 x n2 real array in the given dtype.
  * Supported extents: every n >= 1 whose prime factors are 2, 3, 5 and 7, with
- * n0, n1 <= 4096, n2 even and n2 <= 8192.  Other extents return
+ * n0, n1 <= 4096 and n2 <= 8192 (n2 odd or even).  Other extents return
  * FFT3D_ERR_UNSUPPORTED; n < 1, a bad dtype or out == NULL return
  * FFT3D_ERR_INVALID_ARG.  Builds the radix schedules and the twiddle table
  * (host, FP64 via long double) and uploads the table to the current device
@@ -163,8 +163,9 @@ typedef struct {
  * buffers set up when the first plan on the device was created (8 launches
  * deep; a submit that finds its ring slot still in flight waits for it).
  * Batches of more than 4096 passes are split into several launches.
- * Items whose extents have a factor 5 or 7 run their own kernels (as
- * fft3d_r2c / fft3d_c2r), on the same stream after the batched launch. */
+ * Items whose extents have a factor 5 or 7, or an odd n2, run their own
+ * kernels (as fft3d_r2c / fft3d_c2r), on the same stream after the batched
+ * launch. */
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t stream);
 
 /* flags of fft3d_batch_submit_ex / fft3d_batch_create */
@@ -180,8 +181,9 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
  * and the launch is a hipGraph of one kernel node (instantiated here) unless
  * FFT3D_BATCH_DIRECT.  The item pointers are fixed at creation.  The same
  * concurrency rules as fft3d_batch_submit apply; at most 4096 passes.
- * Items whose extents have a factor 5 or 7 are refused here
- * (FFT3D_ERR_UNSUPPORTED): the batched kernel has only the radix-2/3 stages;
+ * Items whose extents have a factor 5 or 7, or an odd n2, are refused here
+ * (FFT3D_ERR_UNSUPPORTED): the batched kernel has only the radix-2/3 stages
+ * and the half-length rows of even n2;
  * fft3d_batch_submit runs such items with their own kernels, after the
  * batched launch of the others.
  * Launches of one handle must not overlap in time (same stream, or ordered);
@@ -226,7 +228,8 @@ int fft3d_c2r_transposed(fft3d_plan_t p, void* Xt, void* y, void* work, hipStrea
  *     outside the box are never read.  With work (fft3d_work_bytes), X is
  *     left unchanged; without, X is overwritten.
  * Arguments, alignment and overlap rules, and errors as fft3d_r2c /
- * fft3d_c2r; a NULL kmax is FFT3D_ERR_INVALID_ARG. */
+ * fft3d_c2r; a NULL kmax is FFT3D_ERR_INVALID_ARG; plans with odd n2 return
+ * FFT3D_ERR_UNSUPPORTED. */
 int fft3d_r2c_pruned(fft3d_plan_t p, const void* x, void* X, const int64_t kmax[3], hipStream_t stream);
 int fft3d_c2r_pruned(fft3d_plan_t p, void* X, void* y, void* work, const int64_t kmax[3], hipStream_t stream);
 

@@ -525,6 +525,7 @@ namespace {
 int pruned_box(const fft3d::Plan& p, const int64_t* kmax, const char* who, fft3d::PrunedBox& b)
 {
     if (!kmax) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": kmax is NULL");
+    if (p.n2 % 2 != 0) return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": odd n2 is not supported");
     const int64_t K0 = kmax[0], K1 = kmax[1], K2 = kmax[2];
     b.K0 = (K0 < 0 || 2 * K0 + 1 >= p.n0) ? -1 : (int)K0;
     b.K1 = (K1 < 0 || 2 * K1 + 1 >= p.n1) ? -1 : (int)K1;
@@ -581,16 +582,17 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
             if ((rc = run_alone(items[i]))) return rc;
         return FFT3D_OK;
     }
-    // items with radix-5/7 extents run their own kernels, after the batched
-    // launch of the others (the batched kernel has only the 2/3 stages)
+    // items with radix-5/7 extents or odd n2 run their own kernels, after
+    // the batched launch of the others (the batched kernel has only the 2/3
+    // stages and the half-length rows)
     std::vector<fft3d_batch_item> even;
     even.reserve(n);
     for (int i = 0; i < n; ++i)
-        if (!items[i].plan->p.odd) even.push_back(items[i]);
+        if (items[i].plan->p.batchable()) even.push_back(items[i]);
     if ((int)even.size() < n) {
         if (!even.empty() && (rc = fft3d_batch_submit_ex(even.data(), (int)even.size(), 0, s))) return rc;
         for (int i = 0; i < n; ++i)
-            if (items[i].plan->p.odd && (rc = run_alone(items[i]))) return rc;
+            if (!items[i].plan->p.batchable() && (rc = run_alone(items[i]))) return rc;
         return FFT3D_OK;
     }
     fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
@@ -621,9 +623,9 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
     int rc = validate_batch(items, n, who);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
-        if (items[i].plan->p.odd)
+        if (!items[i].plan->p.batchable())
             return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": item " + std::to_string(i) +
-                                                   " has radix-5/7 extents (use fft3d_batch_submit)");
+                                                   " has radix-5/7 extents or odd n2 (use fft3d_batch_submit)");
     fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
     std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
     if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");

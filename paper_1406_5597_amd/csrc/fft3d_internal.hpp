@@ -64,9 +64,12 @@ struct Plan {
     int64_t N = 0;            // n0*n1*n2 real inputs
     int dtype = 0;            // 0 FP32, 1 FP64
     bool odd = false;         // a schedule has radix-5/7 stages: the kernels built with them
+
+    // The batched kernel takes the plan's items (2/3 stages, even n2).
+    bool batchable() const { return !odd && n2 % 2 == 0; }
     int elem = 4;             // bytes per real scalar
 
-    AxisSched ax0{}, ax1{}, ax2h{};  // stage schedules: n0, n1, and h = n2/2
+    AxisSched ax0{}, ax1{}, ax2h{};  // stage schedules: n0, n1, and the rows: h = n2/2 (n2 even) or n2 (odd)
     // Twiddle table (forward roots of unity) in long double, interleaved re, im;
     // offsets in complex elements.  Rounded once to the plan's dtype on upload.
     std::vector<long double> tw_host;
@@ -133,6 +136,11 @@ void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s);
 // Work queues of the cooperative plane step: one per XCD (8 on MI355X; the
 // queue index is the hardware XCC id masked to this many).
 constexpr int kCoopQueues = 16;
+
+// Odd n2: (pair, bin) items per thread in the separation of two real rows
+// from one complex line; the plan caps rows per tile so a tile has at most
+// kNtSmall * kPairItems of them.
+constexpr int kPairItems = 8;
 
 // Box of kept modes of the pruned transforms: |k0| <= K0, |k1| <= K1,
 // 0 <= k2 <= K2.  K0, K1 < 0 keep the whole axis; K2 is in [0, h].

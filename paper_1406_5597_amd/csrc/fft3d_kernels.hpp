@@ -271,6 +271,175 @@ __global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const Axi
     rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, Hs, axh, tw, post, buf);
 }
 
+// ---- odd n2: two real rows per complex line ----
+//
+// With n2 odd there is no half-length complex row.  Rows a = 2p and b = 2p+1
+// of a tile are transformed together as the complex line z = x_a + i x_b of
+// length n2 (Z = DFT z) and then separated, for k = 0 .. H-1 (H = (n2+1)/2):
+//   X_a[k] = (Z[k] + conj Z[n2-k]) / 2,   X_b[k] = (Z[k] - conj Z[n2-k]) / (2i)
+// (Z[n2-0] read as Z[0]).  The inverse builds the line from the two rows of
+// bins, Z[k] = X_a[k] + i X_b[k] and Z[n2-k] = conj X_a[k] + i conj X_b[k]
+// for k >= 1, Z[0] = Re X_a[0] + i Re X_b[0] (the imaginary part of the DC
+// bin is dropped, as the c2r definition does), and takes y_a = Re z,
+// y_b = Im z.  A tile with an odd number of rows pairs its last row with a
+// zero row.  In LDS, pair p's line occupies the two padded rows 2p, 2p+1
+// (line stride 2*Hs), and the separated bins land in those rows.
+
+// Global real rows read as pair lines: line w, element i = (x_a[i], x_b[i]).
+template <typename T> struct PairRowsIn {
+    static constexpr bool kLds = false;
+    static constexpr bool kLinear = true;
+    struct Pos {
+        int off;
+        bool two;  // row b exists
+    };
+    const T* src;
+    int n, rows;
+    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * n + i, 2 * w + 1 < rows}; }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const
+    {
+        p.off += d;
+        return p;
+    }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return mk<T>(src[p.off], p.two ? src[p.off + n] : (T)0); }
+    __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
+};
+
+// Pair lines written out as real rows: y_a[i] = Re, y_b[i] = Im.
+template <typename T> struct PairRowsOut {
+    static constexpr bool kLds = false;
+    static constexpr bool kLinear = true;
+    using Pos = typename PairRowsIn<T>::Pos;
+    T* dst;
+    int n, rows;
+    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * n + i, 2 * w + 1 < rows}; }
+    __device__ __forceinline__ Pos adv(Pos p, int d) const
+    {
+        p.off += d;
+        return p;
+    }
+    __device__ __forceinline__ void put(Pos p, cx<T> v) const
+    {
+        dst[p.off] = v.x;
+        if (p.two) dst[p.off + n] = v.y;
+    }
+    __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+};
+
+// Separation of the pair lines into rows of H bins (all reads, barrier, all
+// writes: the rows overlay the lines).  At most NT * kPairItems (pair, bin)
+// items per tile (the plan caps the rows per tile).  mgH = div_magic(H).
+template <int NT, typename T>
+__device__ __forceinline__ void split_pairs(cx<T>* buf, int rows, int Hs, int n2, int H, uint32_t mgH)
+{
+    const int total = ((rows + 1) / 2) * H;
+    cx<T> xa[kPairItems], xb[kPairItems];
+#pragma unroll
+    for (int u = 0; u < kPairItems; ++u) {
+        const int e = (int)threadIdx.x + u * NT;
+        if (e < total) {
+            const int p = fdiv(e, mgH), k = e - p * H;
+            const cx<T>* Z = buf + 2 * p * Hs;
+            const cx<T> A = Z[pad16(k)], B = Z[pad16(k == 0 ? 0 : n2 - k)];
+            xa[u] = mk<T>((T)0.5 * (A.x + B.x), (T)0.5 * (A.y - B.y));
+            xb[u] = mk<T>((T)0.5 * (A.y + B.y), (T)-0.5 * (A.x - B.x));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPairItems; ++u) {
+        const int e = (int)threadIdx.x + u * NT;
+        if (e < total) {
+            const int p = fdiv(e, mgH), k = e - p * H;
+            buf[2 * p * Hs + pad16(k)] = xa[u];
+            if (2 * p + 1 < rows) buf[(2 * p + 1) * Hs + pad16(k)] = xb[u];
+        }
+    }
+    __syncthreads();
+}
+
+// The reverse: rows of H bins -> pair lines of n2 elements.
+template <int NT, typename T>
+__device__ __forceinline__ void merge_pairs(cx<T>* buf, int rows, int Hs, int n2, int H, uint32_t mgH)
+{
+    const int total = ((rows + 1) / 2) * H;
+    cx<T> zk[kPairItems], zm[kPairItems];
+#pragma unroll
+    for (int u = 0; u < kPairItems; ++u) {
+        const int e = (int)threadIdx.x + u * NT;
+        if (e < total) {
+            const int p = fdiv(e, mgH), k = e - p * H;
+            const cx<T> a = buf[2 * p * Hs + pad16(k)];
+            const cx<T> b = 2 * p + 1 < rows ? buf[(2 * p + 1) * Hs + pad16(k)] : mk<T>((T)0, (T)0);
+            if (k == 0) {
+                zk[u] = mk<T>(a.x, b.x);
+            } else {
+                zk[u] = mk<T>(a.x - b.y, a.y + b.x);
+                zm[u] = mk<T>(a.x + b.y, b.x - a.y);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPairItems; ++u) {
+        const int e = (int)threadIdx.x + u * NT;
+        if (e < total) {
+            const int p = fdiv(e, mgH), k = e - p * H;
+            cx<T>* Z = buf + 2 * p * Hs;
+            Z[pad16(k)] = zk[u];
+            if (k > 0) Z[pad16(n2 - k)] = zm[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Split-plane forward for odd n2: rpw real rows -> rpw rows of H bins.
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_rows_r2c_odd(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
+                                                     const cx<T>* __restrict__ tw, int64_t nrows, int rpw, int Hs,
+                                                     uint32_t mgH, int reverse)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& ax = *axp;  // length n2
+    const int n2 = ax.n, H = n2 / 2 + 1;
+    const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
+    const int64_t left = nrows - row0;
+    const int rows = left < rpw ? (int)left : rpw;
+    PairRowsIn<T> g;
+    g.src = x + row0 * n2;
+    g.n = n2;
+    g.rows = rows;
+    const LdsRowsIO<T> l = lds_rows<T>(buf, 2 * Hs);
+    fft_lines<false, false, NT, EPT, T>(g, l, l, (rows + 1) / 2, 0u, ax, tw);
+    split_pairs<NT, T>(buf, rows, Hs, n2, H, mgH);
+    lds_to_rows<T, NT>(X + row0 * H, buf, rows, H, Hs, mgH);
+}
+
+// Split-plane inverse for odd n2: rpw rows of H bins -> rpw real rows.
+template <typename T, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_rows_c2r_odd(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
+                                                     const cx<T>* __restrict__ tw, int64_t nrows, int rpw, int Hs,
+                                                     uint32_t mgH, int reverse)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const AxisSched& ax = *axp;
+    const int n2 = ax.n, H = n2 / 2 + 1;
+    const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
+    const int64_t left = nrows - row0;
+    const int rows = left < rpw ? (int)left : rpw;
+    rows_to_lds<T, NT>(buf, X + row0 * H, rows, H, Hs, mgH);
+    __syncthreads();
+    merge_pairs<NT, T>(buf, rows, Hs, n2, H, mgH);
+    PairRowsOut<T> g;
+    g.dst = y + row0 * n2;
+    g.n = n2;
+    g.rows = rows;
+    const LdsRowsIO<T> l = lds_rows<T>(buf, 2 * Hs);
+    fft_lines<true, false, NT, EPT, T>(l, l, g, (rows + 1) / 2, 0u, ax, tw);
+}
+
 // np whole n1 x n2 planes (np <= ppw) held in LDS as padded rows
 // [plane][n1][Hs]: forward = rows (from HBM), split, then the n1 columns (to
 // HBM); inverse = n1 columns (from HBM), merge, rows (to HBM).  mg_lines =
@@ -617,6 +786,10 @@ template <typename T> hipError_t init_plain()
     FFT3D_ALLOW((k_rows_r2c<T, kNtBig, EB>));
     FFT3D_ALLOW((k_rows_c2r<T, kNtSmall, ES>));
     FFT3D_ALLOW((k_rows_c2r<T, kNtBig, EB>));
+    FFT3D_ALLOW((k_rows_r2c_odd<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_rows_r2c_odd<T, kNtBig, EB>));
+    FFT3D_ALLOW((k_rows_c2r_odd<T, kNtSmall, ES>));
+    FFT3D_ALLOW((k_rows_c2r_odd<T, kNtBig, EB>));
     FFT3D_ALLOW((k_plane_r2c<T, kNtSmall, ES>));
     FFT3D_ALLOW((k_plane_r2c<T, kNtBig, EB>));
     FFT3D_ALLOW((k_plane_c2r<T, kNtSmall, ES>));
@@ -680,6 +853,16 @@ hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int64_t nrows, int 
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
     const T* xi = static_cast<const T*>(x);
     cx<T>* Xo = static_cast<cx<T>*>(X);
+    if (p.n2 & 1) {
+        const uint32_t mgH = div_magic((uint32_t)p.H);
+        if (p.rows_big)
+            hipLaunchKernelGGL((k_rows_r2c_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
+                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+        else
+            hipLaunchKernelGGL((k_rows_r2c_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, xi,
+                               Xo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+        return hipGetLastError();
+    }
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
                            dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
@@ -696,6 +879,16 @@ hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int 
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
     const cx<T>* Xi = static_cast<const cx<T>*>(X);
     T* yo = static_cast<T*>(y);
+    if (p.n2 & 1) {
+        const uint32_t mgH = div_magic((uint32_t)p.H);
+        if (p.rows_big)
+            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
+                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+        else
+            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
+                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+        return hipGetLastError();
+    }
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
                            dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);

@@ -225,6 +225,25 @@ const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_l
     // lets three FP32 workgroups (two FP64) share a CU -- measured at 512^3:
     // FP32 rows kernels 4.35 -> 4.72 TB/s with 16 rows instead of 32
     const int64_t budget = p.dtype == FFT3D_F64 ? 60 * 1024 : 48 * 1024;
+    if (p.n2 % 2 != 0) {
+        // odd n2: pairs of rows per complex line of n2 elements, an even
+        // number of rows per tile (the last tile pairs its odd row with a
+        // zero row in the slot after it), at most kPairItems (pair, bin)
+        // items per thread in the separation
+        const int64_t pair_cap = std::max<int64_t>(1, (int64_t)kNtSmall * kPairItems / p.H);
+        int64_t pairs = std::min<int64_t>({es / p.n2, budget / (2 * (int64_t)p.Hs * cxs), pair_cap});
+        rows_big = false;
+        if (pairs < 1) {
+            pairs = std::min<int64_t>({eb / p.n2, kLdsMax / (2 * (int64_t)p.Hs * cxs), pair_cap});
+            rows_big = true;
+        }
+        if (pairs < 1) return "n2 too large for one pair of rows in LDS";
+        rpw = (int)std::min<int64_t>(2 * pairs, p.n0 * p.n1);
+        rows_lds = (size_t)((rpw + (rpw & 1)) * p.Hs * cxs);
+        if (!make_colpass(pass1, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, eb))
+            return "n1 too large for a column tile";
+        return nullptr;
+    }
     int64_t r = std::min<int64_t>(es / p.h, budget / ((int64_t)p.Hs * cxs));
     rows_big = false;
     if (r < 1) {
@@ -249,11 +268,6 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         why = "dtype must be FFT3D_F32 or FFT3D_F64";
         return FFT3D_ERR_INVALID_ARG;
     }
-    if (n2 % 2 != 0) {
-        snprintf(msg, sizeof msg, "n2 = %lld is odd; the GPU path needs an even n2", (long long)n2);
-        why = msg;
-        return FFT3D_ERR_UNSUPPORTED;
-    }
     if (n0 > 4096 || n1 > 4096 || n2 > 8192) {
         why = "extents above n0, n1 <= 4096, n2 <= 8192 are not supported";
         return FFT3D_ERR_UNSUPPORTED;
@@ -269,8 +283,11 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     p.N = n0 * n1 * n2;
     p.dtype = dtype;
     p.elem = dtype == FFT3D_F64 ? 8 : 4;
-    if (!make_schedule(n0, p.ax0) || !make_schedule(n1, p.ax1) || !make_schedule(p.h, p.ax2h)) {
-        snprintf(msg, sizeof msg, "extents %lld x %lld x %lld: n0, n1 and n2/2 must have no prime factor other than 2, 3, 5 and 7",
+    // rows: a half-length complex FFT of h = n2/2 for even n2, a full-length
+    // one of n2 (two real rows per complex line) for odd n2
+    const bool n2_odd = n2 % 2 != 0;
+    if (!make_schedule(n0, p.ax0) || !make_schedule(n1, p.ax1) || !make_schedule(n2_odd ? n2 : p.h, p.ax2h)) {
+        snprintf(msg, sizeof msg, "extents %lld x %lld x %lld: n0, n1 and n2 (n2/2 for even n2) must have no prime factor other than 2, 3, 5 and 7",
                  (long long)n0, (long long)n1, (long long)n2);
         why = msg;
         return FFT3D_ERR_UNSUPPORTED;
@@ -307,7 +324,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     const int hs_bank = padded_stride(p.H, true), hs_min = padded_stride(p.H, false);
     p.Hs = hs_bank;
     bool fused = false;
-    for (int big = 0; big < 2 && !fused; ++big) {
+    for (int big = 0; big < 2 && !fused && !n2_odd; ++big) {
         const int64_t emax = big ? eb : es, lmax = big ? kLdsMax : kLdsHalf;
         for (int hs : {hs_bank, hs_min}) {
             if (plane_elems <= emax && n1 * hs * cxs <= lmax) {
@@ -333,7 +350,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         // n1-pass tile width (power of two, at most the tier's)
         if (const char* v = getenv("FFT3D_ROWS_RPW")) {
             const int r = atoi(v);
-            if (r >= 1 && r < p.rpw) {
+            if (r >= 1 && r < p.rpw && !(n2_odd && (r & 1))) {
                 p.rpw = r;
                 p.rows_lds = (size_t)(p.rpw * p.Hs * cxs);
             }
@@ -353,7 +370,8 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         }
         // one cooperative launch for the plane step when both task kinds fit
         // the small tier (and the caller did not ask for the two-kernel path)
-        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1 && !p.odd) {
+        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1 && !p.odd &&
+            !n2_odd) {
             p.coop = true;
             p.coop_rpw = p.rpw;
             p.coop_w = p.pass1.W;

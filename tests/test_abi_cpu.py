@@ -47,7 +47,7 @@ def test_binding_has_no_fallback():
 @pytest.mark.parametrize("shape,dtype,code", [
     ((0, 4, 4), "f32", -1), ((4, -1, 4), "f64", -1), ((4, 4, 0), "f32", -1),
     ((11, 4, 4), "f32", -2), ((4, 13, 4), "f64", -2), ((4, 4, 22), "f32", -2),
-    ((4, 4, 5), "f32", -2), ((4, 4, 7), "f64", -2), ((8192, 4, 4), "f32", -2),
+    ((4, 4, 11), "f32", -2), ((4, 4, 13), "f64", -2), ((4, 4, 44), "f32", -2), ((8192, 4, 4), "f32", -2),
     ((4, 4, 16384), "f32", -2),
 ])
 def test_plan_rejects(F, shape, dtype, code):
