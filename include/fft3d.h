@@ -233,6 +233,17 @@ int fft3d_c2r_transposed(fft3d_plan_t p, void* Xt, void* y, void* work, hipStrea
 int fft3d_r2c_pruned(fft3d_plan_t p, const void* x, void* X, const int64_t kmax[3], hipStream_t stream);
 int fft3d_c2r_pruned(fft3d_plan_t p, void* X, void* y, void* work, const int64_t kmax[3], hipStream_t stream);
 
+/* In-place transforms in FFTW's padded layout: buf holds n0 x n1 rows of
+ * 2*(n2/2+1) reals each, of which the first n2 are the row (the rest is
+ * padding, never read) -- exactly the bytes of the n0 x n1 x (n2/2+1)
+ * complex spectrum, which replaces them (fft3d_r2c_inplace); the reverse for
+ * fft3d_c2r_inplace (the padding of the output rows is left unspecified).
+ * Same kernels as fft3d_r2c / fft3d_c2r (without work): the results are bit
+ * for bit theirs.  Plans with the cooperative plane step run the two-kernel
+ * plane step here.  buf must be aligned to the complex type. */
+int fft3d_r2c_inplace(fft3d_plan_t p, void* buf, hipStream_t stream);
+int fft3d_c2r_inplace(fft3d_plan_t p, void* buf, hipStream_t stream);
+
 /* The passes a transform is made of, for fft3d_run_pass.  The forward
  * transform is PLANE_R2C, N1_FWD (split plans only), N0_FWD (n0 > 1); the
  * inverse is N0_INV (n0 > 1), N1_INV (split plans only), PLANE_C2R.  A plan's

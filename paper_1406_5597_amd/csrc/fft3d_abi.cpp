@@ -559,6 +559,50 @@ int fft3d_c2r_pruned(fft3d_plan_t h, void* X, void* y, void* work, const int64_t
     return FFT3D_OK;
 }
 
+int fft3d_r2c_inplace(fft3d_plan_t h, void* buf, hipStream_t s)
+{
+    const char* who = "fft3d_r2c_inplace";
+    int rc = check_plan(h, who);
+    if (rc) return rc;
+    const fft3d::Plan& p = h->p;
+    if ((rc = check_ptr(buf, 2 * p.elem, who, "buf"))) return rc;
+    // each rows / plane tile reads all of its rows before it writes them back
+    // as bins, and the column passes run in place anyway
+    hipError_t e;
+    if (p.fused_plane) {
+        e = fft3d::launch_plane_r2c(p, buf, buf, s, true);
+    } else {
+        e = fft3d::launch_rows_r2c(p, buf, buf, p.n0 * p.n1, p.rev & 1, s, true);
+        if (e == hipSuccess && p.n1 > 1)
+            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, buf, buf, false, (p.rev >> 1) & 1, s);
+    }
+    if (e == hipSuccess && p.n0 > 1)
+        e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, buf, buf, false, (p.rev >> 2) & 1, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
+int fft3d_c2r_inplace(fft3d_plan_t h, void* buf, hipStream_t s)
+{
+    const char* who = "fft3d_c2r_inplace";
+    int rc = check_plan(h, who);
+    if (rc) return rc;
+    const fft3d::Plan& p = h->p;
+    if ((rc = check_ptr(buf, 2 * p.elem, who, "buf"))) return rc;
+    hipError_t e = hipSuccess;
+    if (p.n0 > 1) e = fft3d::launch_cols(p, p.pass0, 0, p.off_ax0, buf, buf, true, (p.rev >> 3) & 1, s);
+    if (e == hipSuccess) {
+        if (p.fused_plane) {
+            e = fft3d::launch_plane_c2r(p, buf, buf, s, true);
+        } else {
+            if (p.n1 > 1) e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, buf, buf, true, (p.rev >> 4) & 1, s);
+            if (e == hipSuccess) e = fft3d::launch_rows_c2r(p, buf, buf, p.n0 * p.n1, (p.rev >> 5) & 1, s, true);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, who);
+    return FFT3D_OK;
+}
+
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
 {
     return fft3d_batch_submit_ex(items, n, 0, s);

@@ -69,21 +69,23 @@ hipError_t launch_pruned_c2r(const Plan& p, const void* X, void* y, void* work, 
 {
     return FFT3D_PICK(p, launch_pruned_c2r, p, X, y, work, b, st);
 }
-hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st)
+hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t st, bool padded)
 {
-    return FFT3D_PICK(p, launch_plane_r2c, p, x, X, st);
+    return FFT3D_PICK(p, launch_plane_r2c, p, x, X, st, padded);
 }
-hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t st)
+hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t st, bool padded)
 {
-    return FFT3D_PICK(p, launch_plane_c2r, p, X, y, st);
+    return FFT3D_PICK(p, launch_plane_c2r, p, X, y, st, padded);
 }
-hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st)
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st,
+                           bool padded)
 {
-    return FFT3D_PICK(p, launch_rows_r2c, p, x, X, nrows, rev, st);
+    return FFT3D_PICK(p, launch_rows_r2c, p, x, X, nrows, rev, st, padded);
 }
-hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st)
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st,
+                           bool padded)
 {
-    return FFT3D_PICK(p, launch_rows_c2r, p, X, y, nrows, rev, st);
+    return FFT3D_PICK(p, launch_rows_c2r, p, X, y, nrows, rev, st, padded);
 }
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t st)

@@ -154,12 +154,12 @@ struct PrunedBox {
     hipError_t init_coop_##sfx();                                                                          \
     hipError_t coop_occupancy_##sfx(const Plan& p, int* per_cu);                                           \
     hipError_t launch_plane_coop_##sfx(const Plan& p, const void* in, void* out, bool inverse, hipStream_t s); \
-    hipError_t launch_plane_r2c_##sfx(const Plan& p, const void* x, void* X, hipStream_t s);               \
-    hipError_t launch_plane_c2r_##sfx(const Plan& p, const void* X, void* y, hipStream_t s);               \
+    hipError_t launch_plane_r2c_##sfx(const Plan& p, const void* x, void* X, hipStream_t s, bool padded);  \
+    hipError_t launch_plane_c2r_##sfx(const Plan& p, const void* X, void* y, hipStream_t s, bool padded);  \
     hipError_t launch_rows_r2c_##sfx(const Plan& p, const void* x, void* X, int64_t nrows, int rev,        \
-                                     hipStream_t s);                                                       \
+                                     hipStream_t s, bool padded);                                          \
     hipError_t launch_rows_c2r_##sfx(const Plan& p, const void* X, void* y, int64_t nrows, int rev,        \
-                                     hipStream_t s);                                                       \
+                                     hipStream_t s, bool padded);                                          \
     hipError_t launch_cols_##sfx(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, \
                                  void* out, bool inverse, int rev, hipStream_t s);                         \
     hipError_t launch_swap01_##sfx(const Plan& p, const void* in, void* out, int64_t na, int64_t nb, hipStream_t s); \
@@ -176,12 +176,16 @@ FFT3D_DECLARE_DTYPE(f64_odd)
 #undef FFT3D_DECLARE_DTYPE
 
 // Launchers (enqueue on `stream`, no allocation, no synchronisation).
-hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t stream);
-hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t stream);
+// padded: the real array in the in-place layout (rows of 2H reals, n2 used)
+// instead of contiguous rows of n2.
+hipError_t launch_plane_r2c(const Plan& p, const void* x, void* X, hipStream_t stream, bool padded = false);
+hipError_t launch_plane_c2r(const Plan& p, const void* X, void* y, hipStream_t stream, bool padded = false);
 // rev: walk each XCD's chunk of tiles from its end (see xcd_tile).
 // nrows: rows to transform from the given pointers (n0*n1 for a whole array).
-hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t stream);
-hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t stream);
+hipError_t launch_rows_r2c(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t stream,
+                           bool padded = false);
+hipError_t launch_rows_c2r(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t stream,
+                           bool padded = false);
 // axis: 0 = n0, 1 = n1 (index into the plan's device schedules).
 hipError_t launch_cols(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in, void* out,
                        bool inverse, int rev, hipStream_t stream);

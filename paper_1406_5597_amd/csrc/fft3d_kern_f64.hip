@@ -12,21 +12,23 @@
 namespace fft3d {
 
 hipError_t FFT3D_ENTRY(init_plain)() { return init_plain<double>(); }
-hipError_t FFT3D_ENTRY(launch_plane_r2c)(const Plan& p, const void* x, void* X, hipStream_t s)
+hipError_t FFT3D_ENTRY(launch_plane_r2c)(const Plan& p, const void* x, void* X, hipStream_t s, bool padded)
 {
-    return plane_r2c_t<double>(p, x, X, s);
+    return plane_r2c_t<double>(p, x, X, s, padded);
 }
-hipError_t FFT3D_ENTRY(launch_plane_c2r)(const Plan& p, const void* X, void* y, hipStream_t s)
+hipError_t FFT3D_ENTRY(launch_plane_c2r)(const Plan& p, const void* X, void* y, hipStream_t s, bool padded)
 {
-    return plane_c2r_t<double>(p, X, y, s);
+    return plane_c2r_t<double>(p, X, y, s, padded);
 }
-hipError_t FFT3D_ENTRY(launch_rows_r2c)(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t s)
+hipError_t FFT3D_ENTRY(launch_rows_r2c)(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t s,
+                                        bool padded)
 {
-    return rows_r2c_t<double>(p, x, X, nrows, rev, s);
+    return rows_r2c_t<double>(p, x, X, nrows, rev, s, padded);
 }
-hipError_t FFT3D_ENTRY(launch_rows_c2r)(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t s)
+hipError_t FFT3D_ENTRY(launch_rows_c2r)(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t s,
+                                        bool padded)
 {
-    return rows_c2r_t<double>(p, X, y, nrows, rev, s);
+    return rows_c2r_t<double>(p, X, y, nrows, rev, s, padded);
 }
 hipError_t FFT3D_ENTRY(launch_cols)(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, const void* in,
                            void* out, bool inverse, int rev, hipStream_t s)

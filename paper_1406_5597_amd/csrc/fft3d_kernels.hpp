@@ -180,18 +180,19 @@ __device__ __forceinline__ void col_tile(const cx<T>* src, cx<T>* dst, int64_t S
 
 // `rows` real rows of length n2 (read as h = n2/2 complex values
 // z[m] = x[2m] + i x[2m+1]) -> `rows` rows of H = h+1 bins, contiguous.
-// Hs: padded LDS row stride.  LP: cache policy of the input loads, SP: of
+// Hs: padded LDS row stride.  rs: stride of the real rows in complex units
+// (0: h, contiguous rows; H for the padded in-place layout).  LP: cache policy of the input loads, SP: of
 // the output stores.
 template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
 __device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int rows, int Hs, const AxisSched& axh,
                                               const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
-                                              cx<T>* buf)
+                                              cx<T>* buf, int rs = 0)
 {
     const int h = axh.n, H = h + 1;
     RowsIO<T, LP> g;
     g.src = xz;
     g.dst = nullptr;
-    g.len = h;
+    g.len = rs ? rs : h;
     const LdsRowsIO<T> l = lds_rows<T>(buf, Hs);
     fft_lines<false, false, NT, EPT, T>(g, l, l, rows, 0u, axh, tw);
     split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
@@ -203,7 +204,7 @@ __device__ __forceinline__ void rows_r2c_tile(const cx<T>* xz, cx<T>* Xo, int ro
 template <typename T, int NT, int EPT, int LP = LD_PLAIN, int SP = ST_PLAIN>
 __device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int rows, int Hs, const AxisSched& axh,
                                               const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
-                                              cx<T>* buf)
+                                              cx<T>* buf, int rs = 0)
 {
     const int h = axh.n, H = h + 1;
     rows_to_lds<T, NT, LP>(buf, Xi, rows, H, Hs, axh.mg_np1);
@@ -212,7 +213,7 @@ __device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int ro
     RowsIO<T, LD_PLAIN, SP> g;
     g.src = nullptr;
     g.dst = yz;
-    g.len = h;
+    g.len = rs ? rs : h;
     const LdsRowsIO<T> l = lds_rows<T>(buf, Hs);
     fft_lines<true, false, NT, EPT, T>(l, l, g, rows, 0u, axh, tw);
 }
@@ -241,17 +242,17 @@ template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
-                                                 int rpw, int Hs, int reverse)
+                                                 int rpw, int Hs, int reverse, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const AxisSched& axh = *axp;
-    const int h = axh.n, H = h + 1;
+    const int H = axh.n + 1;
     const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
-    rows_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + row0 * h, X + row0 * H, rows, Hs, axh, tw, post,
-                              buf);
+    rows_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + row0 * rs, X + row0 * H, rows, Hs, axh, tw, post,
+                              buf, rs);
 }
 
 // Split-plane inverse: rpw rows of H bins -> rpw real rows of length n2.
@@ -259,16 +260,17 @@ template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
-                                                 int rpw, int Hs, int reverse)
+                                                 int rpw, int Hs, int reverse, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const AxisSched& axh = *axp;
-    const int h = axh.n, H = h + 1;
+    const int H = axh.n + 1;
     const int64_t row0 = (reverse ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x) * rpw;
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
-    rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * h, rows, Hs, axh, tw, post, buf);
+    rows_c2r_tile<T, NT, EPT>(X + row0 * H, reinterpret_cast<cx<T>*>(y) + row0 * rs, rows, Hs, axh, tw, post, buf,
+                              rs);
 }
 
 // ---- odd n2: two real rows per complex line ----
@@ -294,14 +296,14 @@ template <typename T> struct PairRowsIn {
         bool two;  // row b exists
     };
     const T* src;
-    int n, rows;
-    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * n + i, 2 * w + 1 < rows}; }
+    int rs, rows;  // rs: real-row stride (n2, or 2H padded)
+    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * rs + i, 2 * w + 1 < rows}; }
     __device__ __forceinline__ Pos adv(Pos p, int d) const
     {
         p.off += d;
         return p;
     }
-    __device__ __forceinline__ cx<T> get(Pos p) const { return mk<T>(src[p.off], p.two ? src[p.off + n] : (T)0); }
+    __device__ __forceinline__ cx<T> get(Pos p) const { return mk<T>(src[p.off], p.two ? src[p.off + rs] : (T)0); }
     __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
 };
 
@@ -311,8 +313,8 @@ template <typename T> struct PairRowsOut {
     static constexpr bool kLinear = true;
     using Pos = typename PairRowsIn<T>::Pos;
     T* dst;
-    int n, rows;
-    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * n + i, 2 * w + 1 < rows}; }
+    int rs, rows;
+    __device__ __forceinline__ Pos at(int w, int i) const { return Pos{2 * w * rs + i, 2 * w + 1 < rows}; }
     __device__ __forceinline__ Pos adv(Pos p, int d) const
     {
         p.off += d;
@@ -321,7 +323,7 @@ template <typename T> struct PairRowsOut {
     __device__ __forceinline__ void put(Pos p, cx<T> v) const
     {
         dst[p.off] = v.x;
-        if (p.two) dst[p.off + n] = v.y;
+        if (p.two) dst[p.off + rs] = v.y;
     }
     __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
 };
@@ -397,7 +399,7 @@ __device__ __forceinline__ void merge_pairs(cx<T>* buf, int rows, int Hs, int n2
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_r2c_odd(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
                                                      const cx<T>* __restrict__ tw, int64_t nrows, int rpw, int Hs,
-                                                     uint32_t mgH, int reverse)
+                                                     uint32_t mgH, int reverse, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -407,8 +409,8 @@ __global__ __launch_bounds__(NT) void k_rows_r2c_odd(const T* x, cx<T>* X, const
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
     PairRowsIn<T> g;
-    g.src = x + row0 * n2;
-    g.n = n2;
+    g.src = x + row0 * rs;
+    g.rs = rs;
     g.rows = rows;
     const LdsRowsIO<T> l = lds_rows<T>(buf, 2 * Hs);
     fft_lines<false, false, NT, EPT, T>(g, l, l, (rows + 1) / 2, 0u, ax, tw);
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(NT) void k_rows_r2c_odd(const T* x, cx<T>* X, const
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_rows_c2r_odd(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                      const cx<T>* __restrict__ tw, int64_t nrows, int rpw, int Hs,
-                                                     uint32_t mgH, int reverse)
+                                                     uint32_t mgH, int reverse, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -433,8 +435,8 @@ __global__ __launch_bounds__(NT) void k_rows_c2r_odd(const cx<T>* X, T* y, const
     __syncthreads();
     merge_pairs<NT, T>(buf, rows, Hs, n2, H, mgH);
     PairRowsOut<T> g;
-    g.dst = y + row0 * n2;
-    g.n = n2;
+    g.dst = y + row0 * rs;
+    g.rs = rs;
     g.rows = rows;
     const LdsRowsIO<T> l = lds_rows<T>(buf, 2 * Hs);
     fft_lines<true, false, NT, EPT, T>(l, l, g, (rows + 1) / 2, 0u, ax, tw);
@@ -448,14 +450,14 @@ template <typename T, int NT, int EPT>
 __device__ __forceinline__ void plane_r2c_tile(const cx<T>* xz, cx<T>* Xo, int np, const AxisSched& axh,
                                                const AxisSched& ax1, const cx<T>* __restrict__ tw2,
                                                const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw1,
-                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf)
+                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf, int rs = 0)
 {
     const int h = axh.n, H = h + 1, n1 = ax1.n;
     const int rows = np * n1;
     RowsIO<T> gi;
     gi.src = xz;
     gi.dst = nullptr;
-    gi.len = h;
+    gi.len = rs ? rs : h;
     const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
     fft_lines<false, false, NT, EPT, T>(gi, lr, lr, rows, 0u, axh, tw2);
     split_rows<NT, T>(buf, rows, Hs, h, axh.mg_pairs, post);
@@ -473,7 +475,7 @@ template <typename T, int NT, int EPT>
 __device__ __forceinline__ void plane_c2r_tile(const cx<T>* Xi, cx<T>* yz, int np, const AxisSched& axh,
                                                const AxisSched& ax1, const cx<T>* __restrict__ tw2,
                                                const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw1,
-                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf)
+                                               int Hs, uint32_t mg_lines, uint32_t mgH, cx<T>* buf, int rs = 0)
 {
     const int h = axh.n, H = h + 1, n1 = ax1.n;
     const int rows = np * n1;
@@ -489,7 +491,7 @@ __device__ __forceinline__ void plane_c2r_tile(const cx<T>* Xi, cx<T>* yz, int n
     RowsIO<T> go;
     go.src = nullptr;
     go.dst = yz;
-    go.len = h;
+    go.len = rs ? rs : h;
     const LdsRowsIO<T> lr = lds_rows<T>(buf, Hs);
     fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, 0u, axh, tw2);
 }
@@ -501,16 +503,16 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const Ax
                                                   const cx<T>* __restrict__ tw2,
                                                   const cx<T>* __restrict__ post,
                                                   const cx<T>* __restrict__ tw1, int64_t nplanes,
-                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH)
+                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int h = axhp->n, H = h + 1, n1 = ax1p->n;
+    const int H = axhp->n + 1, n1 = ax1p->n;
     const int64_t p0 = (int64_t)blockIdx.x * ppw;
     const int64_t left = nplanes - p0;
     const int np = left < ppw ? (int)left : ppw;
-    plane_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + p0 * n1 * h, X + p0 * n1 * H, np, *axhp, *ax1p,
-                               tw2, post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf);
+    plane_r2c_tile<T, NT, EPT>(reinterpret_cast<const cx<T>*>(x) + p0 * n1 * rs, X + p0 * n1 * H, np, *axhp, *ax1p,
+                               tw2, post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf, rs);
 }
 
 template <typename T, int NT, int EPT>
@@ -519,16 +521,16 @@ __global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const Ax
                                                   const cx<T>* __restrict__ tw2,
                                                   const cx<T>* __restrict__ post,
                                                   const cx<T>* __restrict__ tw1, int64_t nplanes,
-                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH)
+                                                  int ppw, int Hs, uint32_t mg_lines, uint32_t mgH, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int h = axhp->n, H = h + 1, n1 = ax1p->n;
+    const int H = axhp->n + 1, n1 = ax1p->n;
     const int64_t p0 = (int64_t)blockIdx.x * ppw;
     const int64_t left = nplanes - p0;
     const int np = left < ppw ? (int)left : ppw;
-    plane_c2r_tile<T, NT, EPT>(X + p0 * n1 * H, reinterpret_cast<cx<T>*>(y) + p0 * n1 * h, np, *axhp, *ax1p, tw2,
-                               post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf);
+    plane_c2r_tile<T, NT, EPT>(X + p0 * n1 * H, reinterpret_cast<cx<T>*>(y) + p0 * n1 * rs, np, *axhp, *ax1p, tw2,
+                               post, tw1, Hs, np == ppw ? mg_lines : div_magic_dev(np * H), mgH, buf, rs);
 }
 
 // ---- cooperative plane step for planes larger than LDS ----
@@ -806,10 +808,12 @@ template <typename T> hipError_t init_coop()
     return a != hipSuccess ? a : b;
 }
 
+// padded: real rows of 2H reals (the in-place layout) instead of n2.
 template <typename T>
-hipError_t plane_r2c_t(const Plan& p, const void* x, void* X, hipStream_t st)
+hipError_t plane_r2c_t(const Plan& p, const void* x, void* X, hipStream_t st, bool padded = false)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const int rs = (int)(padded ? p.H : p.h);
     const unsigned grid = (unsigned)((p.n0 + p.ppw - 1) / p.ppw);
     const T* xi = static_cast<const T*>(x);
     cx<T>* Xo = static_cast<cx<T>*>(X);
@@ -817,19 +821,20 @@ hipError_t plane_r2c_t(const Plan& p, const void* x, void* X, hipStream_t st)
         hipLaunchKernelGGL((k_plane_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, xi,
                            Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
                            table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
-                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H), rs);
     else
         hipLaunchKernelGGL((k_plane_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
                            xi, Xo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
                            table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
-                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H), rs);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st)
+hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st, bool padded = false)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
+    const int rs = (int)(padded ? p.H : p.h);
     const unsigned grid = (unsigned)((p.n0 + p.ppw - 1) / p.ppw);
     const cx<T>* Xi = static_cast<const cx<T>*>(X);
     T* yo = static_cast<T*>(y);
@@ -837,17 +842,18 @@ hipError_t plane_c2r_t(const Plan& p, const void* X, void* y, hipStream_t st)
         hipLaunchKernelGGL((k_plane_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.plane_lds, st, Xi,
                            yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
                            table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
-                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H), rs);
     else
         hipLaunchKernelGGL((k_plane_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.plane_lds, st,
                            Xi, yo, dsched(p, 2), dsched(p, 1), table<T>(p, p.off_ax2h), table<T>(p, p.off_post),
                            table<T>(p, p.off_ax1), p.n0, p.ppw, p.plane_Hs,
-                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H));
+                           div_magic((uint32_t)(p.ppw * p.H)), div_magic((uint32_t)p.H), rs);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st)
+hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int64_t nrows, int rev, hipStream_t st,
+                      bool padded = false)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
@@ -855,25 +861,29 @@ hipError_t rows_r2c_t(const Plan& p, const void* x, void* X, int64_t nrows, int 
     cx<T>* Xo = static_cast<cx<T>*>(X);
     if (p.n2 & 1) {
         const uint32_t mgH = div_magic((uint32_t)p.H);
+        const int rs = (int)(padded ? 2 * p.H : p.n2);
         if (p.rows_big)
             hipLaunchKernelGGL((k_rows_r2c_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
-                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
         else
             hipLaunchKernelGGL((k_rows_r2c_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, xi,
-                               Xo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+                               Xo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
         return hipGetLastError();
     }
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_r2c<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, xi, Xo,
-                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+                           (int)(padded ? p.H : p.h));
     else
         hipLaunchKernelGGL((k_rows_r2c<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, xi,
-                           Xo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
+                           Xo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+                           (int)(padded ? p.H : p.h));
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st)
+hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int rev, hipStream_t st,
+                      bool padded = false)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
     const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
@@ -881,20 +891,23 @@ hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int 
     T* yo = static_cast<T*>(y);
     if (p.n2 & 1) {
         const uint32_t mgH = div_magic((uint32_t)p.H);
+        const int rs = (int)(padded ? 2 * p.H : p.n2);
         if (p.rows_big)
             hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
         else
             hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev);
+                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
         return hipGetLastError();
     }
     if (p.rows_big)
         hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+                           (int)(padded ? p.H : p.h));
     else
         hipLaunchKernelGGL((k_rows_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev);
+                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+                           (int)(padded ? p.H : p.h));
     return hipGetLastError();
 }
 

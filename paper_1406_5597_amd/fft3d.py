@@ -53,7 +53,7 @@ EXPORTS = (
     "fft3d_batch_launch", "fft3d_batch_status", "fft3d_batch_describe", "fft3d_batch_destroy",
     "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
     "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy", "fft3d_r2c_transposed",
-    "fft3d_c2r_transposed", "fft3d_r2c_pruned", "fft3d_c2r_pruned",
+    "fft3d_c2r_transposed", "fft3d_r2c_pruned", "fft3d_c2r_pruned", "fft3d_r2c_inplace", "fft3d_c2r_inplace",
 )
 
 
@@ -124,6 +124,8 @@ def _load() -> ctypes.CDLL:
         "fft3d_r2c_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fft3d_c2r_transposed": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fft3d_r2c_pruned": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(i64), vp]),
+        "fft3d_r2c_inplace": (ctypes.c_int, [vp, vp, vp]),
+        "fft3d_c2r_inplace": (ctypes.c_int, [vp, vp, vp]),
         "fft3d_c2r_pruned": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
@@ -293,6 +295,14 @@ def fft3d_r2c_pruned(plan: Plan, x, X, kmax, stream=None) -> None:
 
 def fft3d_c2r_pruned(plan: Plan, X, y, kmax, work=None, stream=None) -> None:
     _check(lib.fft3d_c2r_pruned(plan.handle, _addr(X), _addr(y), _addr(work), _kmax(kmax), _stream(stream)))
+
+
+def fft3d_r2c_inplace(plan: Plan, buf, stream=None) -> None:
+    _check(lib.fft3d_r2c_inplace(plan.handle, _addr(buf), _stream(stream)))
+
+
+def fft3d_c2r_inplace(plan: Plan, buf, stream=None) -> None:
+    _check(lib.fft3d_c2r_inplace(plan.handle, _addr(buf), _stream(stream)))
 
 
 def fft3d_batch_submit(items, stream=None) -> None:
