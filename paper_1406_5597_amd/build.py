@@ -28,18 +28,19 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-co
                 "-I" + INCLUDE]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "--offload-arch=" + ARCH, "--cuda-host-only", "-I" + INCLUDE]
 
+# Longest compiles first (they bound the wall time; the pool runs one per core).
 SOURCES = [
-    ("fft3d_coop_f32.hip", DEVICE_FLAGS),
-    ("fft3d_coop_f64.hip", DEVICE_FLAGS),
-    ("fft3d_kern_f32.hip", DEVICE_FLAGS),
-    ("fft3d_kern_f64.hip", DEVICE_FLAGS),
-    ("fft3d_batch.hip", DEVICE_FLAGS),
-    ("fft3d_pruned_f32.hip", DEVICE_FLAGS),
-    ("fft3d_pruned_f64.hip", DEVICE_FLAGS),
     ("fft3d_kern_f32_odd.hip", DEVICE_FLAGS),
     ("fft3d_kern_f64_odd.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f32.hip", DEVICE_FLAGS),
+    ("fft3d_kern_f64.hip", DEVICE_FLAGS),
     ("fft3d_pruned_f32_odd.hip", DEVICE_FLAGS),
     ("fft3d_pruned_f64_odd.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f32.hip", DEVICE_FLAGS),
+    ("fft3d_pruned_f64.hip", DEVICE_FLAGS),
+    ("fft3d_batch.hip", DEVICE_FLAGS),
+    ("fft3d_coop_f32.hip", DEVICE_FLAGS),
+    ("fft3d_coop_f64.hip", DEVICE_FLAGS),
     ("fft3d_batch_host.cpp", HOST_FLAGS),
     ("fft3d_server.cpp", HOST_FLAGS),
     ("fft3d_plan.cpp", HOST_FLAGS),
@@ -63,7 +64,8 @@ def _compile(src: str, flags) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, int(os.environ.get("MAX_JOBS", "64"))))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
