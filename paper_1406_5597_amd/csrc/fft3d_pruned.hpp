@@ -53,10 +53,14 @@ template <typename T> struct ColTileMaskIO {
         p.row += d;
         return p;
     }
+    // Every lane loads (a masked row from the tile's first element, which is
+    // cached) so that the loads of a stage stay in flight together; masked
+    // rows then read as zero.
     __device__ __forceinline__ cx<T> get(Pos p) const
     {
-        if (!p.ok || !kept(p.row, n, kin)) return mk<T>((T)0, (T)0);
-        return src[p.off];
+        const bool keep = p.ok && kept(p.row, n, kin);
+        const cx<T> v = src[keep ? p.off : 0];
+        return keep ? v : mk<T>((T)0, (T)0);
     }
     __device__ __forceinline__ void put(Pos p, cx<T> v) const
     {
@@ -98,8 +102,9 @@ template <typename T> struct PlaneColsMaskIO {
     }
     __device__ __forceinline__ cx<T> get(Pos p) const
     {
-        if (!p.ok || !kept(p.row, n1, K1)) return mk<T>((T)0, (T)0);
-        return src[p.off];
+        const bool keep = p.ok && kept(p.row, n1, K1);
+        const cx<T> v = src[keep ? p.off : 0];
+        return keep ? v : mk<T>((T)0, (T)0);
     }
     __device__ __forceinline__ void put(Pos p, cx<T> v) const
     {
@@ -195,26 +200,24 @@ __global__ __launch_bounds__(NT) void k_rows_c2r_pr(const cx<T>* X, T* y, const 
     const int64_t left = nrows - row0;
     const int rows = left < rpw ? (int)left : rpw;
     const cx<T>* src = X + row0 * H;
-    // kept bins: 8 loads in flight per thread before the LDS stores
+    // kept bins: 8 loads in flight per thread before the LDS stores.  Lanes
+    // past the end repeat the last bin (same value to the same slot), so
+    // loads and stores are unconditional and the loads are not serialised.
     constexpr int U = 8;
     const int count = rows * Hw;
     for (int base = 0; base < count; base += U * NT) {
         cx<T> v[U];
+        int slot[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = base + (int)threadIdx.x + u * NT;
-            const int ec = e < count ? e : count - 1;  // always a kept bin
-            const int q = fdiv(ec, mgHw);
-            v[u] = src[(int64_t)q * H + (ec - q * Hw)];
+            const int ec = e < count ? e : count - 1;
+            const int q = fdiv(ec, mgHw), c = ec - q * Hw;
+            v[u] = src[(int64_t)q * H + c];
+            slot[u] = q * Hs + pad16(c);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + (int)threadIdx.x + u * NT;
-            if (e < count) {
-                const int q = fdiv(e, mgHw);
-                buf[q * Hs + pad16(e - q * Hw)] = v[u];
-            }
-        }
+        for (int u = 0; u < U; ++u) buf[slot[u]] = v[u];
     }
     // the other bins are zero
     const int nz = H - Hw, zcount = rows * nz;
