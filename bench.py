@@ -90,6 +90,18 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
 
+    # spread: the same number of pairs again, an event after every pair
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    marks[0].record(s)
+    for i in range(steps):
+        pair()
+        marks[i + 1].record(s)
+    torch.cuda.synchronize()
+    per = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+
+    def pct(q):
+        return per[min(len(per) - 1, int(round(q * (len(per) - 1))))]
+
     # per-kernel: the same pairs, pass by pass, an event pair around each kernel
     seq = [(p, x, X) if p == 0 else (p, X, X) for p in desc["r2c_passes"]]
     cur = X
@@ -127,6 +139,7 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     out = {
         "pairs_s": 1e3 / ms,
         "ms_per_pair": ms,
+        "pair_ms_p10_p50_p90": [round(pct(0.1), 4), round(pct(0.5), 4), round(pct(0.9), 4)],
         "hbm_frac_alg": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "hbm_frac_min": b_min / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "GB_s_alg": b_alg / (ms * 1e-3) / 1e9,
@@ -465,7 +478,7 @@ def main() -> int:
     ap.add_argument("--no-pruned", action="store_true", help="skip the pruned (two-thirds box) pair")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s) of the served stream")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per served rate")
-    ap.add_argument("--serve-warmup", type=float, default=5.0, help="seconds of unmeasured arrivals first")
+    ap.add_argument("--serve-warmup", type=float, default=10.0, help="seconds of unmeasured arrivals first")
     ap.add_argument("--coop-plane", action="store_true",
                     help="cooperative one-launch plane step for large planes instead of the two kernels")
     args = ap.parse_args()
@@ -561,6 +574,17 @@ def main() -> int:
             results[d]["rel_l2_r2c"] = fields.rel_l2(Xd.cpu().numpy(), Xo)
             results[d]["rel_l2_c2r"] = fields.rel_l2(yd.cpu().numpy(), yo)
         del Xo, yo
+        # smaller configurations, one thread and all threads (seconds per pair)
+        small = {}
+        for m in (32, 256):
+            xs = fields.uniform((m, m, m), 1)
+            row = {}
+            for th in (1, 0):
+                t1 = time.time()
+                oracle.c2r(oracle.r2c(xs, th), m, th)
+                row["threads_%d" % (th or oracle.max_threads())] = round(time.time() - t1, 4)
+            small["%d^3" % m] = row
+        cpu["pair_seconds_fp64"] = small
 
     traffic = recorded_traffic()
     for d in dtypes:
@@ -580,6 +604,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_pair"], 4),
+        "pair_ms_p10_p50_p90": r["pair_ms_p10_p50_p90"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -609,6 +634,7 @@ def main() -> int:
     for d in dtypes[1:]:
         o = results[d]
         line[d] = {"value": round(o["pairs_s"], 2), "unit": "pairs/s", "ms_per_step": round(o["ms_per_pair"], 4),
+                   "pair_ms_p10_p50_p90": o["pair_ms_p10_p50_p90"],
                    "hbm_frac_alg": round(o["hbm_frac_alg"], 4), "hbm_frac_min": round(o["hbm_frac_min"], 4),
                    "gflops": round(o["gflops"], 1), "kernels": o["kernels"], "roofline": o["roofline"]}
     print(json.dumps(line), flush=True)
