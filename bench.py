@@ -203,19 +203,40 @@ def run_ablation(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
             "n0_columns_exchanged_layout_us": round(n0t_us, 1)}
 
 
-def pruned_pair_bytes_alg(shape, elem: int, kmax) -> int:
-    """Algorithmic HBM bytes of a pruned pair on the split plane path: each
-    pass reads and writes only the lines and rows inside the box (forward:
-    rows write K2+1 bins, the n1 pass keeps 2K1+1 rows, the n0 pass 2K0+1;
-    the inverse mirrors it)."""
+def _box_counts(shape, kmax):
     n0, n1, n2 = shape
     K0, K1, K2 = kmax
     hw = n2 // 2 + 1 if K2 < 0 or K2 >= n2 // 2 else K2 + 1
     m1 = n1 if K1 < 0 or 2 * K1 + 1 >= n1 else 2 * K1 + 1
     m0 = n0 if K0 < 0 or 2 * K0 + 1 >= n0 else 2 * K0 + 1
+    return hw, m1, m0
+
+
+def pruned_pair_bytes_alg(shape, elem: int, kmax) -> int:
+    """B_alg of a pruned pair, in the same accounting as pair_bytes_alg (each
+    of the paper's two steps reads and writes once): step 1 reads the real
+    array and writes the kept (k1, k2) of every plane, step 3 reads those and
+    writes the kept box; the inverse mirrors it."""
+    n0, n1, n2 = shape
+    hw, m1, m0 = _box_counts(shape, kmax)
     c = 2 * elem
-    fwd = elem * n0 * n1 * n2 + c * (n0 * n1 * hw + n0 * n1 * hw + n0 * m1 * hw + n0 * m1 * hw + m0 * m1 * hw)
-    return 2 * fwd
+    return 2 * (elem * n0 * n1 * n2 + c * (2 * n0 * m1 * hw + m0 * m1 * hw))
+
+
+def pruned_pair_bytes_swept(shape, elem: int, kmax) -> int:
+    """Bytes a pruned pair moves on the split plane path (rows kernel, n1
+    pass, n0 pass, each reading and writing only inside the box)."""
+    n0, n1, n2 = shape
+    hw, m1, m0 = _box_counts(shape, kmax)
+    c = 2 * elem
+    return 2 * (elem * n0 * n1 * n2 + c * (2 * n0 * n1 * hw + 2 * n0 * m1 * hw + m0 * m1 * hw))
+
+
+def pair_bytes_swept(shape, elem: int) -> int:
+    """Bytes a full pair moves on the split plane path (three sweeps)."""
+    n0, n1, n2 = shape
+    M = n0 * n1 * (n2 // 2 + 1)
+    return 2 * (elem * n0 * n1 * n2 + 5 * 2 * elem * M)
 
 
 def run_pruned(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
@@ -246,11 +267,13 @@ def run_pruned(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
     ms = e0.elapsed_time(e1) / steps
     elem = 4 if dtype == "f32" else 8
     b = pruned_pair_bytes_alg(shape, elem, kmax)
+    bs = pruned_pair_bytes_swept(shape, elem, kmax)
     del x, X, y, work
     return {"kmax": list(kmax), "ms_per_pair": round(ms, 4), "pairs_s": round(1e3 / ms, 2),
             "full_ms_per_pair": round(free_ms, 4), "speedup_vs_full": round(free_ms / ms, 3),
             "bytes_alg": b, "bytes_ratio_vs_full": round(b / pair_bytes_alg(shape, elem), 3),
-            "GB_s_alg": round(b / (ms * 1e-3) / 1e9, 1)}
+            "bytes_swept": bs, "swept_ratio_vs_full": round(bs / pair_bytes_swept(shape, elem), 3),
+            "GB_s_alg": round(b / (ms * 1e-3) / 1e9, 1), "GB_s_swept": round(bs / (ms * 1e-3) / 1e9, 1)}
 
 
 def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
