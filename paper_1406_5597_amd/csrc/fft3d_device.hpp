@@ -23,7 +23,7 @@
 // Radix-5 and radix-7 stages are compiled into the kernels only when
 // FFT3D_ODD_RADICES is 1: their extra cases in the stage dispatch raise the
 // register count of every kernel, so 2^a 3^b extents keep kernels without
-// them.  The two builds live in different inline namespaces, so both sets of
+// them.  The two compilations live in different inline namespaces, so both sets of
 // kernels link into one library.
 #ifndef FFT3D_ODD_RADICES
 #define FFT3D_ODD_RADICES 0

@@ -5,7 +5,7 @@
 
 namespace fft3d {
 
-// The entry point of the plan's dtype, from the build with radix-5/7 stages
+// The entry point of the plan's dtype, from the kernels compiled with radix-5/7 stages
 // when the plan has them.
 #define FFT3D_PICK(p, name, ...)                                                                   \
     ((p).dtype ? ((p).odd ? name##_f64_odd(__VA_ARGS__) : name##_f64(__VA_ARGS__))                 \

@@ -169,7 +169,7 @@ struct PrunedBox {
                                        hipStream_t s);
 FFT3D_DECLARE_DTYPE(f32)
 FFT3D_DECLARE_DTYPE(f64)
-// the builds with radix-5/7 stages (fft3d_kern_*_odd.hip, fft3d_pruned_*_odd.hip;
+// the kernels compiled with radix-5/7 stages (fft3d_kern_*_odd.hip, fft3d_pruned_*_odd.hip;
 // no cooperative kernel)
 FFT3D_DECLARE_DTYPE(f32_odd)
 FFT3D_DECLARE_DTYPE(f64_odd)

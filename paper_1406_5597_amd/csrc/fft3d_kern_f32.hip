@@ -2,7 +2,7 @@
 // (plane, rows, strided columns); see fft3d_kernels.hpp.
 #include "fft3d_kernels.hpp"
 
-// entry points of this build: name_f32, or name_f32_odd with the radix-5/7 stages
+// entry points defined here: name_f32, or name_f32_odd when the radix-5/7 stages are compiled in
 #if FFT3D_ODD_RADICES
 #define FFT3D_ENTRY(name) name##_f32_odd
 #else

@@ -2,7 +2,7 @@
 // see fft3d_pruned.hpp.
 #include "fft3d_pruned.hpp"
 
-// entry points of this build: name_f64, or name_f64_odd with the radix-5/7 stages
+// entry points defined here: name_f64, or name_f64_odd when the radix-5/7 stages are compiled in
 #if FFT3D_ODD_RADICES
 #define FFT3D_ENTRY(name) name##_f64_odd
 #else
