@@ -138,3 +138,32 @@ def test_pruned_errors(F):
         F.fft3d_r2c_pruned(plan, x, x, (5, 5, 5))
     with pytest.raises(ValueError):
         F.fft3d_r2c_pruned(plan, x, X, (5, 5))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_pruned_512cubed_bench_configuration(F, oracle, dtype):
+    """The benchmark's pruned pair (512^3, K = 170 on every axis): bit for bit
+    against the full transforms on the whole box, and sampled kept modes
+    against the oracle's one-value evaluator."""
+    import torch
+    shape = (512, 512, 512)
+    kmax = (170, 170, 170)
+    say("pruned 512^3 %s" % dtype)
+    plan = F.Plan(*shape, dtype=dtype)
+    x = rounded(fields.uniform(shape, seed=71), dtype)
+    xd = dev_real(x, dtype)
+    Xf = F.r2c(plan, xd)
+    Xp = F.r2c_pruned(plan, xd, kmax)
+    mask = torch.from_numpy(oracle.box_mask(shape, kmax)).to("cuda")
+    assert bool((Xp[mask] == Xf[mask]).all())
+    for k in [(0, 0, 0), (170, 342, 170), (342, 170, 1), (5, 500, 99)]:
+        want = oracle.r2c_point(x, k)
+        got = complex(Xp[k].item())
+        scale = np.sqrt(np.sum(x.astype(np.float64) ** 2))
+        assert abs(got - want) / scale <= (1e-12 if dtype == "f64" else 5e-6), (k, got, want)
+    Xf[~mask] = 0
+    y_full = F.c2r(plan, Xf, work=F.empty_complex(plan))
+    del Xf
+    yp = F.c2r_pruned(plan, Xp, kmax, work=F.empty_complex(plan))
+    torch.cuda.synchronize()
+    assert bool((yp == y_full).all())
