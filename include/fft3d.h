@@ -24,9 +24,9 @@
  *     (k0*n1 + k1)*(n2/2+1) + k2, index k >= n/2 standing for k - n;
  *   - c2r of an arbitrary half spectrum X returns Re(IDFT3(E(X))), where E
  *     completes the k2 axis with E[k0,k1,n2-k2] = conj(X[-k0,-k1,k2]) and
- *     keeps the k2 = 0 and k2 = n2/2 planes as given (equivalently: the
- *     imaginary parts of the k2 = 0 and n2/2 bins of each row are dropped
- *     after the n0 and n1 inverse passes).
+ *     keeps the k2 = 0 plane (and, for even n2, the k2 = n2/2 plane) as given
+ *     (equivalently: the imaginary parts of those bins of each row are
+ *     dropped after the n0 and n1 inverse passes).
  *
  * Memory and threads:
  *   - every array is device memory owned by the caller; a plan owns only its
@@ -75,7 +75,7 @@ enum {
     FFT3D_ERR_UNSUPPORTED = -2, /* extents the GPU path does not cover */
     FFT3D_ERR_NOMEM = -3,       /* plan table allocation failed */
     FFT3D_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch error) */
-    FFT3D_ERR_BUDGET = -5,      /* reserved for admission control */
+    FFT3D_ERR_BUDGET = -5,      /* a server request needs more than the server's memory budget */
     FFT3D_ERR_ALIGN = -6        /* a pointer is not aligned to the plan's complex type */
 };
 
@@ -100,7 +100,9 @@ int fft3d_version(void);
  * FFT3D_ERR_UNSUPPORTED; n < 1, a bad dtype or out == NULL return
  * FFT3D_ERR_INVALID_ARG.  Builds the radix schedules and the twiddle table
  * (host, FP64 via long double) and uploads the table to the current device
- * (hipMalloc + hipMemcpy: the only allocation the library makes).
+ * (hipMalloc + hipMemcpy).  The library allocates only here, in
+ * fft3d_batch_create and in fft3d_server_create: the transforms themselves
+ * allocate nothing.
  * On success *out receives the plan. */
 int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out);
 
@@ -151,9 +153,10 @@ typedef struct {
 /* Run every item in ONE persistent kernel launch on `stream` (the batched
  * form of the plane step and the strided n0 step, Sec. 2.1-2.2, over many
  * fields at once).  Each item becomes a chain of passes (the ones fft3d_r2c /
- * fft3d_c2r would launch); workgroups take tiles of all chains from one
- * global ticket counter, a pass waiting only for the previous pass of the same
- * item.  Every result is bit-identical to the item run alone.
+ * fft3d_c2r would launch); workgroups take tiles of all chains from ticket
+ * counters (one per XCD when items are placed on XCDs, else one for all), a
+ * pass waiting only for the previous pass of the same item.  Every result is
+ * bit-identical to the item run alone.
  * Items run CONCURRENTLY: a buffer one item writes (out, mid, work, and in
  * for C2R without work) must not overlap any buffer of another item; inputs
  * that are only read may be shared.  Plans must outlive the launch.
@@ -284,8 +287,9 @@ int fft3d_plan_describe(fft3d_plan_t p, char* buf, size_t len);
 
 /* Copy the plan's twiddle table for one axis to host memory, as FP64 values of
  * the table exactly as the kernels use it (rounded to the plan's dtype).
- * which: 0 = n0 stages, 1 = n1 stages, 2 = n2/2 stages, 3 = r2c split roots
- * exp(-2 pi i k/n2) for k = 0..n2/2.  out: 2*count doubles (re, im).
+ * which: 0 = n0 stages, 1 = n1 stages, 2 = row stages (length n2/2 for even
+ * n2, n2 for odd n2), 3 = r2c split roots exp(-2 pi i k/n2) for k = 0..n2/2
+ * (used for even n2 only).  out: 2*count doubles (re, im).
  * Returns the number of complex entries of that table, or a negative code;
  * copies min(count, entries). */
 int64_t fft3d_plan_twiddles(fft3d_plan_t p, int which, double* out, int64_t count);
