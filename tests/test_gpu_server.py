@@ -144,3 +144,28 @@ def test_server_budget_error_and_reuse(F):
             F.copy_from_device(got, outs[0], got.numel() * got.element_size())
             assert bool((got == want).all())
             srv.release(i)
+
+
+def test_server_radix57_and_odd_n2_requests(F):
+    """Requests whose plans the batched kernel does not take (radix-5/7
+    extents, odd n2) are served through the batch submit's own-kernel path:
+    bit for bit the transforms run alone."""
+    import torch
+    say("server: radix-5/7 and odd n2")
+    shapes = [((35, 45, 28), "f32"), ((16, 16, 15), "f64"), ((32, 32, 32), "f32")]
+    with F.Server(1 << 30, nstreams=2, batch_points=1 << 20) as srv:
+        for i, (s, d) in enumerate(shapes):
+            p = F.Plan(*s, dtype=d)
+            xs = [dev_real(fields.as_dtype(fields.uniform(s, 600 + 3 * i + c), d), d) for c in range(3)]
+            want = [F.r2c(p, x) for x in xs]
+            torch.cuda.synchronize()
+            rid = srv.submit(s, d, F.FFT3D_R2C, xs)
+            assert srv.wait(rid, 30.0)
+            outs, _ = srv.result(rid, 3)
+            for c in range(3):
+                got = torch.empty_like(want[c])
+                F.copy_from_device(got, outs[c], got.numel() * got.element_size())
+                assert bool((got == want[c]).all()), (s, d, c)
+            srv.release(rid)
+        st = srv.stats()
+    assert st["batched_launches"] >= 1
