@@ -100,8 +100,10 @@ struct Plan {
     // Passes that walk their tiles in reverse (each XCD from its last group),
     // one bit per pass: 1 rows r2c, 2 n1 forward, 4 n0 forward, 8 n0 inverse,
     // 16 n1 inverse, 32 rows c2r.  A pass that reads what the previous pass
-    // wrote last first finds more of it still in the memory-side cache.
-    int rev = 2 | 16;
+    // wrote last first finds more of it still in the memory-side cache
+    // (measured at 512^3: the n1 passes and the inverse n0 pass reversed,
+    // 0.7% faster pairs than the n1 passes alone).
+    int rev = 2 | 8 | 16;
     int64_t coop_ctr_count = 0;
     int* d_ctr = nullptr;
     AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h
