@@ -27,9 +27,10 @@ def all_23_smooth(limit):
     return sorted(out)
 
 
-# Every axis length the GPU path is run at (2^a 3^b up to 1024), plus a few
-# lengths with other primes: the oracle itself accepts any n.
-LENGTHS = all_23_smooth(1024) + [5, 7, 10, 11, 13, 15, 35, 49, 97]
+# Every 2^a 3^b length up to 1024, lengths with factors 5 and 7 (the GPU
+# path's radix-5/7 stages), and a few with other primes: the oracle itself
+# accepts any n.
+LENGTHS = all_23_smooth(1024) + [5, 7, 10, 11, 13, 15, 25, 35, 49, 97, 125, 175, 245, 343, 625, 2401]
 
 
 def rel(a, b):
@@ -150,7 +151,7 @@ def test_point_values_match_numpy_at_64(oracle):
 # ------------------------------------------------ independent library ----
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (64, 48, 40), (96, 32, 64), (27, 12, 18), (16, 16, 9),
-                                   (48, 48, 48), (128, 128, 128)])
+                                   (48, 48, 48), (128, 128, 128), (35, 49, 50), (25, 14, 45)])
 def test_r2c_c2r_match_pocketfft(oracle, shape):
     x = fields.uniform(shape, seed=17)
     X = oracle.r2c(x)
