@@ -611,6 +611,11 @@ def main() -> int:
                 oracle.c2r(oracle.r2c(xs, th), m, th)
                 row["threads_%d" % (th or oracle.max_threads())] = round(time.time() - t1, 4)
             small["%d^3" % m] = row
+        # the benchmark size on one thread (one pair), beside the all-thread rate above
+        t1 = time.time()
+        oracle.c2r(oracle.r2c(xin, 1), n, 1)
+        small["%d^3" % n] = {"threads_1": round(time.time() - t1, 3), "threads_%d" % oracle.max_threads():
+                             round(1.0 / cpu["value"], 3)}
         cpu["pair_seconds_fp64"] = small
 
     traffic = recorded_traffic()
