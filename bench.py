@@ -311,8 +311,19 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    def ring_submit():
+        # the submit never waits: with every ring slot in flight it returns
+        # FFT3D_ERR_BUSY, and the caller tries again
+        while True:
+            try:
+                return F.fft3d_batch_submit(items, s)
+            except F.Fft3dError as e:
+                if e.code != F.FFT3D_ERR_BUSY:
+                    raise
+                time.sleep(1e-4)
+
     ms_graph = timed(lambda: handle.launch(s))
-    ms_ring = timed(lambda: F.fft3d_batch_submit(items, s))
+    ms_ring = timed(ring_submit)
     ms_seq = timed(lambda: F.fft3d_batch_submit_ex(items, F.FFT3D_BATCH_SEQUENTIAL, s))
     status = handle.status()
     desc = handle.describe()
@@ -518,8 +529,9 @@ def main() -> int:
     import torch
 
     from paper_1406_5597_amd import fft3d as F
-    from paper_1406_5597_amd import fields
+    from workloads import fields
 
+    F.fft3d_init()  # the device's batch ring
     n = args.size
     shape = (n, n, n)
     t0 = time.time()

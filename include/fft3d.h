@@ -31,12 +31,14 @@
  * Memory and threads:
  *   - every array is device memory owned by the caller; a plan owns only its
  *     twiddle table (device) and its host description;
- *   - fft3d_r2c, fft3d_c2r and fft3d_batch_submit allocate nothing and do
- *     not synchronise: they enqueue kernels on the given stream and return
- *     (fft3d_batch_submit waits only if its ring slot, 8 launches back, is
- *     still running); the first plan created on a device also sets up that
- *     device's batch ring (about 4 MB device + 4 MB pinned host, kept until
- *     the process ends);
+ *   - fft3d_r2c, fft3d_c2r and fft3d_batch_submit allocate nothing and
+ *     never wait for the device: they enqueue kernels on the given stream
+ *     and return (fft3d_batch_submit returns FFT3D_ERR_BUSY, enqueuing
+ *     nothing, when all 16 slots of its staging ring are still in flight);
+ *   - the library allocates device or pinned memory only in fft3d_init (the
+ *     device's batch ring: about 9 MB device + 9 MB pinned host, kept until
+ *     the process ends), fft3d_plan / fft3d_plan_ex (the plan's tables),
+ *     fft3d_batch_create and fft3d_server_create;
  *   - a plan is immutable after creation and may be used from several
  *     streams or host threads at once, as long as every concurrent call has
  *     its own output and work buffers -- except a plan whose plane step is
@@ -76,7 +78,9 @@ enum {
     FFT3D_ERR_NOMEM = -3,       /* plan table allocation failed */
     FFT3D_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch error) */
     FFT3D_ERR_BUDGET = -5,      /* a server request needs more than the server's memory budget */
-    FFT3D_ERR_ALIGN = -6        /* a pointer is not aligned to the plan's complex type */
+    FFT3D_ERR_ALIGN = -6,       /* a pointer is not aligned to the plan's complex type */
+    FFT3D_ERR_BUSY = -7         /* every slot of the batch staging ring is in flight, or a batched
+                                   launch asked about has not finished: nothing was done, try again */
 };
 
 /* Transform directions of a batch item. */
@@ -94,15 +98,30 @@ enum {
 /* Library version (major*10000 + minor*100 + patch). */
 int fft3d_version(void);
 
-/* Create a plan for an n0 x n1 x n2 real array in the given dtype.
+/* Set up the current device for batched launches (the batched form of the
+ * paper's two steps, Sec. 2.1-2.2, over many fields): finds the device's
+ * XCDs (one probe launch, synchronous) and allocates the staging ring of
+ * fft3d_batch_submit (16 slots of a task image and a counter block: about
+ * 9 MB of device memory and 9 MB of pinned host memory, kept until the
+ * process ends).  Call it once per device, with that device current, before
+ * fft3d_batch_submit / fft3d_batch_create on it (they return
+ * FFT3D_ERR_INVALID_ARG otherwise); further calls do nothing.  Plans and the
+ * single-field transforms do not need it; fft3d_server_create calls it.
+ * Returns FFT3D_OK, FFT3D_ERR_HIP or FFT3D_ERR_NOMEM. */
+int fft3d_init(void);
+
+/* Create a plan for the transforms of an n0 x n1 x n2 real array in the
+ * given dtype (the operation of Sec. 2; like the FFTW plans the paper's
+ * implementation builds its two steps on, Sec. 2.2, a plan is made once per
+ * shape and reused).
  * Supported extents: every n >= 1 whose prime factors are 2, 3, 5 and 7, with
  * n0, n1 <= 4096 and n2 <= 8192 (n2 odd or even).  Other extents return
  * FFT3D_ERR_UNSUPPORTED; n < 1, a bad dtype or out == NULL return
  * FFT3D_ERR_INVALID_ARG.  Builds the radix schedules and the twiddle table
  * (host, FP64 via long double) and uploads the table to the current device
- * (hipMalloc + hipMemcpy).  The library allocates only here, in
- * fft3d_batch_create and in fft3d_server_create: the transforms themselves
- * allocate nothing.
+ * (hipMalloc + hipMemcpy, synchronous).  The library allocates only here, in
+ * fft3d_init, fft3d_batch_create and fft3d_server_create: the transforms
+ * themselves allocate nothing.
  * On success *out receives the plan. */
 int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out);
 
@@ -116,7 +135,10 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
  * sure no enqueued work still uses the plan. */
 int fft3d_plan_destroy(fft3d_plan_t p);
 
-/* Bytes of the optional c2r work buffer: n0*n1*(n2/2+1) complex values. */
+/* Bytes of the optional c2r work buffer: n0*n1*(n2/2+1) complex values --
+ * the spectrum's size (Sec. 2: n0 x n1 x (n2/2+1) complex), into which the
+ * inverse's first step (the n0 columns, Sec. 2.1 run in reverse) writes when
+ * the input spectrum is to be kept.  0 for a NULL plan. */
 size_t fft3d_work_bytes(fft3d_plan_t p);
 /* Bytes of the real array (n0*n1*n2 reals) and of the spectrum. */
 size_t fft3d_real_bytes(fft3d_plan_t p);
@@ -151,8 +173,9 @@ typedef struct {
 } fft3d_batch_item;
 
 /* Run every item in ONE persistent kernel launch on `stream` (the batched
- * form of the plane step and the strided n0 step, Sec. 2.1-2.2, over many
- * fields at once).  Each item becomes a chain of passes (the ones fft3d_r2c /
+ * form of the plane step and the strided n0 step, Sec. 2.1 items 1 and 3,
+ * Sec. 2.2, over many fields at once).  Requires fft3d_init on the items'
+ * device.  Each item becomes a chain of passes (the ones fft3d_r2c /
  * fft3d_c2r would launch); workgroups take tiles of all chains from ticket
  * counters (one per XCD when items are placed on XCDs, else one for all), a
  * pass waiting only for the previous pass of the same item.  Every result is
@@ -162,10 +185,13 @@ typedef struct {
  * that are only read may be shared.  Plans must outlive the launch.
  * All items are validated first; if any is invalid nothing is enqueued (all
  * or nothing) and fft3d_last_error() names the first bad item.
- * No allocation: the task list is staged through a ring of pinned/device
- * buffers set up when the first plan on the device was created (8 launches
- * deep; a submit that finds its ring slot still in flight waits for it).
- * Batches of more than 4096 passes are split into several launches.
+ * No allocation and no wait: the task list is staged through the ring of
+ * pinned/device buffers fft3d_init set up (16 launches deep); a submit that
+ * finds fewer free slots than it needs returns FFT3D_ERR_BUSY and enqueues
+ * nothing.  Batches of more than 4096 passes are split into several
+ * launches (one slot each).  The batched kernel's error bits (see
+ * fft3d_batch_status) are kept per launch: fft3d_batch_submit_checked
+ * returns a token to read them with.
  * Items whose extents have a factor 5 or 7, or an odd n2, run their own
  * kernels (as fft3d_r2c / fft3d_c2r), on the same stream after the batched
  * launch. */
@@ -178,6 +204,17 @@ enum {
     FFT3D_BATCH_DIRECT = 4      /* fft3d_batch_create only: launch with hipLaunchKernel instead of a graph */
 };
 int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipStream_t stream);
+
+/* As fft3d_batch_submit; *token receives a number for fft3d_batch_check (-1
+ * when no batched launch was staged, e.g. only radix-5/7 or odd-n2 items). */
+int fft3d_batch_submit_checked(const fft3d_batch_item* items, int n, hipStream_t stream, int64_t* token);
+/* Error bits of the batched launch(es) a token names, without waiting: 0
+ * clean, else bit 1 (a dependency wait hit its spin limit: tiles skipped)
+ * and/or bit 2 (a ticket queue had no workgroup on its XCD: its items did
+ * not run) -- the results of such a launch are not valid.  FFT3D_ERR_BUSY
+ * while the launch has not finished; FFT3D_ERR_INVALID_ARG for an unknown
+ * token or one older than the last 256 ring launches of its device. */
+int fft3d_batch_check(int64_t token);
 
 /* A batch built once and launched many times: the task list and its counters
  * live in device memory owned by the handle (allocated here, synchronously),
@@ -195,7 +232,9 @@ typedef struct fft3d_batch_s* fft3d_batch_t;
 int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_batch_t* out);
 int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
 /* Error bits of the last finished launch (synchronises the device):
- * 0 = clean, 1 = a dependency wait hit its spin limit (its tiles skipped). */
+ * 0 = clean, bit 1 = a dependency wait hit its spin limit (its tiles
+ * skipped), bit 2 = a ticket queue had no workgroup on its XCD (its items
+ * did not run). */
 int fft3d_batch_status(fft3d_batch_t b);
 /* JSON: items, tickets, grid, LDS bytes, graph, and the tasks in ticket
  * order as [kind, dtype, tiles, index of the task waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
@@ -275,9 +314,11 @@ enum {
  * Returns FFT3D_ERR_INVALID_ARG for a pass the plan does not have. */
 int fft3d_run_pass(fft3d_plan_t p, int pass, const void* in, void* out, hipStream_t stream);
 
-/* Static message for an error code. */
+/* Static message for an error code (the failure conventions of every entry
+ * point above). */
 const char* fft3d_strerror(int code);
-/* Thread-local message of the last failing call on this thread ("" if none). */
+/* Thread-local message of the last failing call on this thread ("" if none);
+ * valid until the next failing call on the thread. */
 const char* fft3d_last_error(void);
 
 /* JSON description of the plan (extents, schedules, strategy, tile widths,

@@ -404,11 +404,6 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
             fft3d_plan_destroy(h);
             return hip_fail(e, "fft3d_plan: schedule upload");
         }
-        e = fft3d::ring_init(dev);
-        if (e != hipSuccess) {
-            fft3d_plan_destroy(h);
-            return fail(FFT3D_ERR_NOMEM, std::string("fft3d_plan: batch ring set-up: ") + hipGetErrorString(e));
-        }
         e = fft3d::coop_setup(h->p);
         if (e != hipSuccess) {
             fft3d_plan_destroy(h);
@@ -603,14 +598,31 @@ int fft3d_c2r_inplace(fft3d_plan_t h, void* buf, hipStream_t s)
     return FFT3D_OK;
 }
 
+int fft3d_init(void)
+{
+    std::call_once(g_init_once, [] { g_init_status = fft3d::kernels_init(); });
+    if (g_init_status != hipSuccess) return hip_fail(g_init_status, "fft3d_init: kernel set-up");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "fft3d_init: hipGetDevice");
+    e = fft3d::ring_init(dev);
+    if (e != hipSuccess) return fail(FFT3D_ERR_NOMEM, std::string("fft3d_init: batch ring: ") + hipGetErrorString(e));
+    return FFT3D_OK;
+}
+
 int fft3d_batch_submit(const fft3d_batch_item* items, int n, hipStream_t s)
 {
     return fft3d_batch_submit_ex(items, n, 0, s);
 }
 
-int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipStream_t s)
+namespace {
+
+// The batched launch of fft3d_batch_submit_ex / _checked; *token (if not
+// NULL) names the ring launches it staged, or -1 when it staged none.
+int batch_submit_impl(const fft3d_batch_item* items, int n, int flags, hipStream_t s, int64_t* token)
 {
     const char* who = "fft3d_batch_submit";
+    if (token) *token = -1;
     if (flags & ~FFT3D_BATCH_SEQUENTIAL)
         return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": unknown flags");
     int rc = validate_batch(items, n, who);
@@ -633,27 +645,61 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
     even.reserve(n);
     for (int i = 0; i < n; ++i)
         if (items[i].plan->p.batchable()) even.push_back(items[i]);
-    if ((int)even.size() < n) {
-        if (!even.empty() && (rc = fft3d_batch_submit_ex(even.data(), (int)even.size(), 0, s))) return rc;
-        for (int i = 0; i < n; ++i)
-            if (!items[i].plan->p.batchable() && (rc = run_alone(items[i]))) return rc;
-        return FFT3D_OK;
-    }
-    fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
-    // items in chunks whose task lists fit a ring slot (6 passes per item at most)
-    const int chunk = fft3d::kRingTasks / 6;
-    for (int i0 = 0; i0 < n; i0 += chunk) {
-        const int m = std::min(chunk, n - i0);
-        std::vector<fft3d::BatchSpec> specs = batch_specs(items + i0, m);
-        fft3d::BatchTable tab;
-        if (const char* why = fft3d::build_batch_table(specs.data(), m, o, tab))
-            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
+    const int device = items[0].plan->p.device;
+    if (!even.empty()) {
+        if (!fft3d::ring_ready(device))
+            return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": fft3d_init() has not been called on device " +
+                                                   std::to_string(device));
+        const fft3d::BatchOptions o = batch_options(device);
+        // items in chunks whose task lists fit a ring slot (6 passes per item at most)
+        const int chunk = fft3d::kRingTasks / 6;
+        const int m = (int)even.size();
+        std::vector<fft3d::BatchTable> tabs;
+        for (int i0 = 0; i0 < m; i0 += chunk) {
+            const int k = std::min(chunk, m - i0);
+            std::vector<fft3d::BatchSpec> specs = batch_specs(even.data() + i0, k);
+            tabs.emplace_back();
+            if (const char* why = fft3d::build_batch_table(specs.data(), k, o, tabs.back()))
+                return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
+        }
         const char* why = nullptr;
-        hipError_t e = fft3d::ring_submit(items[0].plan->p.device, tab, s, &why);
+        int64_t seq = -1;
+        hipError_t e = fft3d::ring_submit(device, tabs.data(), (int)tabs.size(), s, &seq, &why);
+        if (e == hipErrorNotReady) return fail(FFT3D_ERR_BUSY, std::string(who) + ": " + why);
         if (why) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": " + why);
         if (e != hipSuccess) return hip_fail(e, who);
+        if (token) *token = ((int64_t)device << 56) | ((int64_t)tabs.size() << 48) | seq;
     }
+    for (int i = 0; i < n; ++i)
+        if (!items[i].plan->p.batchable() && (rc = run_alone(items[i]))) return rc;
     return FFT3D_OK;
+}
+
+}  // namespace
+
+int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipStream_t s)
+{
+    return batch_submit_impl(items, n, flags, s, nullptr);
+}
+
+int fft3d_batch_submit_checked(const fft3d_batch_item* items, int n, hipStream_t s, int64_t* token)
+{
+    if (!token) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_submit_checked: token is NULL");
+    return batch_submit_impl(items, n, 0, s, token);
+}
+
+int fft3d_batch_check(int64_t token)
+{
+    if (token == -1) return 0;  // nothing was staged through the ring
+    if (token < 0) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_check: bad token");
+    const int device = (int)(token >> 56);
+    const int count = (int)((token >> 48) & 0xff);
+    const int64_t seq = token & (((int64_t)1 << 48) - 1);
+    const char* why = nullptr;
+    const int r = fft3d::ring_status(device, seq, count, &why);
+    if (r < 0 && why) return fail(r, std::string("fft3d_batch_check: ") + why);
+    if (r == FFT3D_ERR_BUSY) return fail(r, "fft3d_batch_check: the launch has not finished");
+    return r;
 }
 
 int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_batch_t* out)
@@ -670,6 +716,9 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
         if (!items[i].plan->p.batchable())
             return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": item " + std::to_string(i) +
                                                    " has radix-5/7 extents or odd n2 (use fft3d_batch_submit)");
+    if (!fft3d::ring_ready(items[0].plan->p.device))
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": fft3d_init() has not been called on device " +
+                                               std::to_string(items[0].plan->p.device));
     fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
     std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
     if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");
@@ -840,6 +889,7 @@ const char* fft3d_strerror(int code)
     case FFT3D_ERR_HIP: return "HIP runtime error";
     case FFT3D_ERR_BUDGET: return "over the memory budget";
     case FFT3D_ERR_ALIGN: return "misaligned pointer";
+    case FFT3D_ERR_BUSY: return "busy: try again later";
     default: return "unknown error code";
     }
 }

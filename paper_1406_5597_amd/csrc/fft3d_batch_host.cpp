@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 
 #include "../../include/fft3d.h"
 
@@ -386,15 +387,24 @@ struct Slot {
     void* host = nullptr;  // pinned staging of the task image
     void* dev = nullptr;   // device task image
     int* ctr = nullptr;    // device counter block (left zeroed by each launch)
+    int* hstat = nullptr;  // pinned: the launch's error bits, copied back behind it
     hipEvent_t done = nullptr;
     bool used = false;
+    int64_t seq = -1;      // sequence number of the slot's last launch
 };
+
+// Error bits of completed launches whose slots were reused since, by
+// sequence number (the last kRingHistory of them).
+constexpr int kRingHistory = 256;
 
 struct Ring {
     int device = -1;
     int next = 0;
+    int64_t seq = 0;           // launches staged so far
     std::vector<int> xcc_ids;  // distinct hardware XCC ids of the device
     Slot slots[kRingSlots];
+    int64_t hist_seq[kRingHistory];
+    int hist_err[kRingHistory];
     std::mutex mu;
 };
 
@@ -409,6 +419,39 @@ Ring* ring_of(int device)
     return nullptr;
 }
 
+void free_slots(Ring& r)
+{
+    for (Slot& q : r.slots) {
+        if (q.host) (void)hipHostFree(q.host);
+        if (q.hstat) (void)hipHostFree(q.hstat);
+        if (q.dev) (void)hipFree(q.dev);
+        if (q.ctr) (void)hipFree(q.ctr);
+        if (q.done) (void)hipEventDestroy(q.done);
+        q = Slot{};
+    }
+}
+
+// State of a slot as the host sees it, without waiting.
+int slot_state(const Slot& sl, hipError_t* err)
+{
+    *err = hipSuccess;
+    if (!sl.used) return kSlotFree;
+    const hipError_t e = hipEventQuery(sl.done);
+    if (e == hipErrorNotReady) return kSlotBusy;
+    if (e != hipSuccess) *err = e;
+    return kSlotDone;
+}
+
+// Record the error bits of a slot's completed launch before it is reused.
+void retire(Ring& r, Slot& sl)
+{
+    if (!sl.used || sl.seq < 0) return;
+    const int i = (int)(sl.seq % kRingHistory);
+    r.hist_seq[i] = sl.seq;
+    r.hist_err[i] = *sl.hstat;
+    sl.used = false;
+}
+
 }  // namespace
 
 hipError_t ring_init(int device)
@@ -418,6 +461,10 @@ hipError_t ring_init(int device)
         if (r->device == device) return hipSuccess;
     std::unique_ptr<Ring> r(new Ring);
     r->device = device;
+    for (int i = 0; i < kRingHistory; ++i) {
+        r->hist_seq[i] = -1;
+        r->hist_err[i] = 0;
+    }
     // the XCDs the device dispatches to (a probe launch of 1024 workgroups)
     std::vector<int> ids(1024);
     hipError_t pe = probe_xcc_ids(1024, ids.data());
@@ -429,23 +476,22 @@ hipError_t ring_init(int device)
     const size_t ctr = (size_t)(kBatchCtrHeader + kRingTasks) * sizeof(int);
     for (Slot& s : r->slots) {
         hipError_t e = hipHostMalloc(&s.host, img, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s.hstat), sizeof(int), hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc(&s.dev, img);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s.ctr), ctr);
         if (e == hipSuccess) e = hipMemset(s.ctr, 0, ctr);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e != hipSuccess) {
-            for (Slot& q : r->slots) {
-                if (q.host) (void)hipHostFree(q.host);
-                if (q.dev) (void)hipFree(q.dev);
-                if (q.ctr) (void)hipFree(q.ctr);
-                if (q.done) (void)hipEventDestroy(q.done);
-            }
+            free_slots(*r);
             return e;
         }
+        *s.hstat = 0;
     }
     g_rings.push_back(std::move(r));
     return hipSuccess;
 }
+
+bool ring_ready(int device) { return ring_of(device) != nullptr; }
 
 std::vector<int> device_xcc_ids(int device)
 {
@@ -453,34 +499,106 @@ std::vector<int> device_xcc_ids(int device)
     return r ? r->xcc_ids : std::vector<int>();
 }
 
-hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const char** why)
+int ring_pick(const int* state, int nslots, int next, int needed, int* picked)
+{
+    int got = 0;
+    for (int k = 0; k < nslots && got < needed; ++k) {
+        const int i = (next + k) % nslots;
+        if (state[i] != kSlotBusy) picked[got++] = i;
+    }
+    return got;
+}
+
+hipError_t ring_submit(int device, const BatchTable* tabs, int ntabs, hipStream_t s, int64_t* first_seq,
+                       const char** why)
 {
     *why = nullptr;
     Ring* r = ring_of(device);
     if (!r) {
-        *why = "no batch ring on this device (create a plan on it first)";
+        *why = "the device has no batch ring: call fft3d_init() on it first";
         return hipErrorInvalidValue;
     }
-    if ((int)tab.tasks.size() > kRingTasks) {
-        *why = "too many tasks for one ring slot";
+    if (ntabs < 1 || ntabs > kRingSlots) {
+        *why = "batch needs more ring slots than the ring has";
         return hipErrorInvalidValue;
     }
-    unsigned grid = 0;
-    hipError_t e = batch_grid(tab, device, &grid);
-    if (e != hipSuccess) return e;
+    std::vector<unsigned> grids((size_t)ntabs);
+    for (int t = 0; t < ntabs; ++t) {
+        if ((int)tabs[t].tasks.size() > kRingTasks) {
+            *why = "too many tasks for one ring slot";
+            return hipErrorInvalidValue;
+        }
+        hipError_t e = batch_grid(tabs[t], device, &grids[(size_t)t]);
+        if (e != hipSuccess) return e;
+    }
     std::lock_guard<std::mutex> g(r->mu);
-    Slot& sl = r->slots[r->next];
-    r->next = (r->next + 1) % kRingSlots;
-    // the slot's previous launch must be done with its staging and counters
-    // (normally long since: the ring is kRingSlots deep)
-    if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return e;
-    write_batch_image(tab, sl.host);
-    const size_t bytes = batch_image_bytes(tab);
-    e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = enqueue_batch_image(tab, grid, sl.dev, sl.ctr, s);
-    if (e == hipSuccess) e = hipEventRecord(sl.done, s);
-    sl.used = e == hipSuccess;
-    return e;
+    // every slot this submit needs must be free or finished: a slot still in
+    // flight is never waited for (all or nothing: nothing is enqueued then)
+    int state[kRingSlots], picked[kRingSlots];
+    for (int i = 0; i < kRingSlots; ++i) {
+        hipError_t qe;
+        state[i] = slot_state(r->slots[i], &qe);
+        if (qe != hipSuccess) return qe;
+    }
+    if (ring_pick(state, kRingSlots, r->next, ntabs, picked) < ntabs) {
+        *why = "every ring slot is still in flight";
+        return hipErrorNotReady;
+    }
+    *first_seq = r->seq;
+    for (int t = 0; t < ntabs; ++t) {
+        Slot& sl = r->slots[picked[t]];
+        retire(*r, sl);
+        write_batch_image(tabs[t], sl.host);
+        const size_t bytes = batch_image_bytes(tabs[t]);
+        hipError_t e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = enqueue_batch_image(tabs[t], grids[(size_t)t], sl.dev, sl.ctr, s);
+        // the launch's error bits, back to the host behind it
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl.hstat, sl.ctr + kBatchCtrStatus, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(sl.done, s);
+        if (e != hipSuccess) return e;
+        sl.used = true;
+        sl.seq = r->seq++;
+        r->next = (picked[t] + 1) % kRingSlots;
+    }
+    return hipSuccess;
+}
+
+int ring_status(int device, int64_t first_seq, int count, const char** why)
+{
+    *why = nullptr;
+    Ring* r = ring_of(device);
+    if (!r) {
+        *why = "the device has no batch ring";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> g(r->mu);
+    int err = 0;
+    for (int64_t q = first_seq; q < first_seq + count; ++q) {
+        bool found = false;
+        for (Slot& sl : r->slots) {
+            if (sl.used && sl.seq == q) {
+                hipError_t qe;
+                const int st = slot_state(sl, &qe);
+                if (qe != hipSuccess) {
+                    *why = hipGetErrorString(qe);
+                    return FFT3D_ERR_HIP;
+                }
+                if (st == kSlotBusy) return FFT3D_ERR_BUSY;
+                err |= *sl.hstat;
+                found = true;
+                break;
+            }
+        }
+        if (found) continue;
+        const int i = (int)(q % kRingHistory);
+        if (q < 0 || q >= r->seq || r->hist_seq[i] != q) {
+            *why = "unknown or expired batch token";
+            return FFT3D_ERR_INVALID_ARG;
+        }
+        err |= r->hist_err[i];
+    }
+    return err;
 }
 
 }  // namespace fft3d

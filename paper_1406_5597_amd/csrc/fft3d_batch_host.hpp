@@ -48,7 +48,7 @@ constexpr int kBatchSpinLimit = 1 << 20;
 // LDS of one batch tile: half a CU's LDS less the kernel's own (scheduling
 // words and the cached ticket table), so that two workgroups fit on a CU.
 constexpr int64_t kBatchLdsCap = kLdsHalf - 2560;
-constexpr int kRingSlots = 8;     // task images fft3d_batch_submit may have in flight per device
+constexpr int kRingSlots = 16;    // task images fft3d_batch_submit may have in flight per device
 constexpr int kRingTasks = 4096;  // tasks per ring slot
 
 // Task list of n items; nullptr or why it cannot be built.
@@ -66,11 +66,26 @@ hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void*
                                hipStream_t s);
 
 // The per-device ring of task images behind fft3d_batch_submit: set up once
-// per device (at plan creation), then each submit stages its image in pinned
-// memory, copies it on the stream and launches, with no allocation.
+// per device (fft3d_init), then each submit stages its image in pinned
+// memory, copies it on the stream and launches, with no allocation and no
+// wait: a submit that finds no slot free or finished returns at once.
 hipError_t ring_init(int device);
+bool ring_ready(int device);
 // Distinct hardware XCC ids of the device (found by ring_init), or empty.
 std::vector<int> device_xcc_ids(int device);
-hipError_t ring_submit(int device, const BatchTable& tab, hipStream_t s, const char** why);
+// Slot states of the submit ring as the host sees them.
+enum RingSlotState { kSlotFree = 0, kSlotDone = 1, kSlotBusy = 2 };
+// Picks up to `needed` slots in ring order from `next`, skipping the ones in
+// flight; returns how many it found (their indexes in picked[]).
+int ring_pick(const int* state, int nslots, int next, int needed, int* picked);
+// Stage and launch ntabs task lists (all or nothing): hipErrorNotReady with
+// *why set when fewer than ntabs slots are free or finished, nothing
+// enqueued.  *first_seq: sequence number of the first launch (the others
+// follow), for ring_status.
+hipError_t ring_submit(int device, const BatchTable* tabs, int ntabs, hipStream_t s, int64_t* first_seq,
+                       const char** why);
+// Error bits (ORed) of the launches first_seq .. first_seq+count-1, once
+// finished; FFT3D_ERR_BUSY while one still runs; a negative code if unknown.
+int ring_status(int device, int64_t first_seq, int count, const char** why);
 
 }  // namespace fft3d

@@ -57,6 +57,7 @@ struct Unit {
     hipEvent_t ev = nullptr;
     int stream = 0;
     double load = 0;  // estimated bytes the unit moves
+    int64_t token = -1;  // batched launch: its ring token (error bits read at completion)
     std::vector<int64_t> reqs;
 };
 
@@ -192,7 +193,13 @@ struct fft3d_server_s {
                         items.push_back({q.plan, q.r.dir, q.r.in[c], nullptr, at(q.out_off[c]),
                                          q.has_work ? at(q.work_off[c]) : nullptr});
                 }
-                rc = fft3d_batch_submit(items.data(), (int)items.size(), s);
+                rc = fft3d_batch_submit_checked(items.data(), (int)items.size(), s, &u.token);
+                // every ring slot in flight: the same items through their own
+                // kernels instead (nothing was enqueued; the submit never waits)
+                if (rc == FFT3D_ERR_BUSY) {
+                    batched = false;
+                    rc = fft3d_batch_submit_ex(items.data(), (int)items.size(), FFT3D_BATCH_SEQUENTIAL, s);
+                }
             } else {
                 for (int64_t id : ids) {
                     Req& q = *reqs[id];
@@ -248,8 +255,18 @@ struct fft3d_server_s {
                     ++it;
                     continue;
                 }
-                for (int64_t id : it->reqs)
-                    finish(*reqs[id], e == hipSuccess, e == hipSuccess ? "" : hipGetErrorString(e));
+                std::string why = e == hipSuccess ? "" : hipGetErrorString(e);
+                if (e == hipSuccess && it->token != -1) {
+                    // the batched kernel's error bits (a dependency wait that
+                    // ran out, a queue without workgroups): its results are void
+                    const int bits = fft3d_batch_check(it->token);
+                    if (bits != 0) {
+                        e = hipErrorUnknown;
+                        why = bits < 0 ? std::string("batched launch: ") + fft3d_last_error()
+                                       : "batched launch reported error bits " + std::to_string(bits);
+                    }
+                }
+                for (int64_t id : it->reqs) finish(*reqs[id], e == hipSuccess, why);
                 if (it->ev) free_events.push_back(it->ev);
                 if (!no_device) stream_load[(size_t)it->stream] -= it->load;
                 it = inflight.erase(it);
@@ -353,7 +370,10 @@ int fft3d_server_create(const fft3d_server_config* cfg, fft3d_server_t* out)
         s->base = reinterpret_cast<void*>((uintptr_t)1 << 44);
     } else {
         hipError_t e = hipGetDevice(&s->device);
-        if (e == hipSuccess) e = hipMalloc(&s->base, s->arena.size());
+        if (e != hipSuccess) return fail(FFT3D_ERR_HIP, std::string("fft3d_server_create: ") + hipGetErrorString(e));
+        // the device's batch ring (allocated once per device)
+        if (int rc = fft3d_init()) return rc;
+        e = hipMalloc(&s->base, s->arena.size());
         if (e != hipSuccess) {
             s->base = nullptr;
             return fail(FFT3D_ERR_NOMEM, std::string("fft3d_server_create: arena: ") + hipGetErrorString(e));

@@ -24,6 +24,7 @@ FFT3D_ERR_NOMEM = -3
 FFT3D_ERR_HIP = -4
 FFT3D_ERR_BUDGET = -5
 FFT3D_ERR_ALIGN = -6
+FFT3D_ERR_BUSY = -7
 FFT3D_R2C = 0
 FFT3D_C2R = 1
 FFT3D_ROUNDTRIP = 2
@@ -54,6 +55,7 @@ EXPORTS = (
     "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
     "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy", "fft3d_r2c_transposed",
     "fft3d_c2r_transposed", "fft3d_r2c_pruned", "fft3d_c2r_pruned", "fft3d_r2c_inplace", "fft3d_c2r_inplace",
+    "fft3d_init", "fft3d_batch_submit_checked", "fft3d_batch_check",
 )
 
 
@@ -92,6 +94,10 @@ def _load() -> ctypes.CDLL:
     i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     sig = {
         "fft3d_version": (ctypes.c_int, []),
+        "fft3d_init": (ctypes.c_int, []),
+        "fft3d_batch_submit_checked": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp,
+                                                      ctypes.POINTER(i64)]),
+        "fft3d_batch_check": (ctypes.c_int, [i64]),
         "fft3d_plan": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.POINTER(vp)]),
         "fft3d_plan_ex": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
         "fft3d_plan_destroy": (ctypes.c_int, [vp]),
@@ -175,6 +181,11 @@ def _stream(s) -> int:
 
 def fft3d_version() -> int:
     return lib.fft3d_version()
+
+
+def fft3d_init() -> None:
+    """Set up the current device for batched launches (its batch ring)."""
+    _check(lib.fft3d_init())
 
 
 class Plan:
@@ -312,6 +323,19 @@ def fft3d_batch_submit(items, stream=None) -> None:
 
 def fft3d_batch_submit_ex(items, flags: int = 0, stream=None) -> None:
     _check(lib.fft3d_batch_submit_ex(_items(items), len(items), int(flags), _stream(stream)))
+
+
+def fft3d_batch_submit_checked(items, stream=None) -> int:
+    """As fft3d_batch_submit; returns the token for fft3d_batch_check."""
+    tok = ctypes.c_int64()
+    _check(lib.fft3d_batch_submit_checked(_items(items), len(items), _stream(stream), ctypes.byref(tok)))
+    return tok.value
+
+
+def fft3d_batch_check(token: int) -> int:
+    """Error bits of a finished batched launch (0 clean); raises Fft3dError
+    (code FFT3D_ERR_BUSY) while it runs."""
+    return _check(lib.fft3d_batch_check(int(token)))
 
 
 class Batch:

@@ -71,8 +71,36 @@ static void span(const void* ptr, int64_t off, int64_t count, int es, uintptr_t&
     n = (size_t)(count * es);
 }
 
+// "ring": the slot choice of the submit ring (ring_pick) on fixed slot
+// states.  A submit must take only free or finished slots, in ring order
+// from the next one, and report a shortfall instead of waiting for a slot in
+// flight.
+static int ring_check()
+{
+    const int F = kSlotFree, D = kSlotDone, B = kSlotBusy;
+    int picked[8];
+    {
+        const int st[4] = {B, B, B, B};  // all in flight: nothing to take
+        if (ring_pick(st, 4, 1, 1, picked) != 0) return fail("ring: took a slot in flight");
+    }
+    {
+        const int st[4] = {B, D, B, F};  // from slot 2: 3 (free), then 1 (finished)
+        if (ring_pick(st, 4, 2, 2, picked) != 2 || picked[0] != 3 || picked[1] != 1)
+            return fail("ring: wrong slots for a two-slot submit");
+        if (ring_pick(st, 4, 2, 3, picked) != 2) return fail("ring: three slots found where two are usable");
+    }
+    {
+        const int st[4] = {F, F, F, F};
+        if (ring_pick(st, 4, 3, 4, picked) != 4 || picked[0] != 3 || picked[1] != 0 || picked[3] != 2)
+            return fail("ring: free slots not taken in ring order");
+    }
+    printf("ok ring\n");
+    return 0;
+}
+
 int main(int argc, char** argv)
 {
+    if (argc > 1 && !strcmp(argv[1], "ring")) return ring_check();
     int G = argc > 1 ? atoi(argv[1]) : 64;
     std::vector<Plan> plans;
     std::vector<int> dirs, works;

@@ -8,7 +8,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -39,7 +39,16 @@ def sim(tmp_path_factory):
         assert p.returncode == 0 and out.startswith("ok"), out + p.stderr
         _, tasks, tickets, lds, pinned = out.split()
         return int(tasks), int(tickets), int(lds), bool(int(pinned))
+    run.exe = exe
     return run
+
+
+def test_busy_ring_returns_instead_of_waiting(sim):
+    """fft3d_batch_submit's slot choice: slots still in flight are skipped,
+    never waited for; too few usable slots is reported (the submit then
+    returns FFT3D_ERR_BUSY with nothing enqueued)."""
+    p = subprocess.run([sim.exe, "ring"], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 0 and p.stdout.strip() == "ok ring", p.stdout + p.stderr
 
 
 def item(shape, dtype, direction, work=1):

@@ -6,7 +6,7 @@ one case per dtype is also checked against the oracle."""
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 from tests.gpu_util import TOL, dev_real, host, rel_l2, rounded, say
 
 pytestmark = pytest.mark.gpu

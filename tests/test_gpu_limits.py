@@ -5,7 +5,7 @@ trip over the whole array where it does not."""
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 from tests.gpu_util import TOL, dev_real, host, rel_l2, rounded, say
 
 pytestmark = pytest.mark.gpu

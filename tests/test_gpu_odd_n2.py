@@ -6,7 +6,7 @@ batched entry points bit for bit against the plain transforms."""
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 from tests.gpu_util import TOL, dev_cplx, dev_real, host, rel_l2, rounded, say
 
 pytestmark = pytest.mark.gpu
@@ -18,6 +18,7 @@ def F():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1406_5597_amd import fft3d
+    fft3d.fft3d_init()  # the device's batch ring
     return fft3d
 
 

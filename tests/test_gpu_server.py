@@ -10,7 +10,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 from tests.gpu_util import TOL, dev_cplx, dev_real, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu

@@ -10,7 +10,7 @@ the oracle fails at least one of them.
 import numpy as np
 import pytest
 
-from paper_1406_5597_amd import fields
+from workloads import fields
 
 pytestmark = []
 
@@ -86,6 +86,49 @@ def test_fft1d_matches_naive_at_every_length(oracle):
             assert r < 1e-14, (n, sign, r)
     # expected accuracy ~ eps * sqrt(log n)
     assert worst < 2e-15
+
+
+def smooth2357(lo, hi):
+    out = []
+    for a in range(14):
+        for b in range(9):
+            for c in range(6):
+                for d in range(5):
+                    n = 2 ** a * 3 ** b * 5 ** c * 7 ** d
+                    if lo < n <= hi:
+                        out.append(n)
+    return sorted(out)
+
+
+# Lengths above 1024 at which the GPU tests use the oracle as the reference
+# (n2 rows of 1536 .. 8192, n1 columns of 2048 and 4096, n0 columns of 4096,
+# radix-5/7 lines of 1400 and 2401): every 2^a 3^b 5^c 7^d length in
+# (1024, 8192] against numpy's pocketfft, an independent library.
+LONG = smooth2357(1024, 8192)
+
+
+def test_fft1d_matches_numpy_at_long_lengths(oracle):
+    rng = np.random.default_rng(8)
+    worst = 0.0
+    for n in LONG:
+        x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        r = rel(oracle.fft1d(x, -1), np.fft.fft(x))
+        ri = rel(oracle.fft1d(x, +1), np.fft.ifft(x) * n)
+        worst = max(worst, r, ri)
+        assert r < 1e-14 and ri < 1e-14, (n, r, ri)
+    assert worst < 4e-15
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [1400, 1536, 2048, 3072, 4096, 8192])
+def test_fft1d_matches_naive_at_long_lengths(oracle, n):
+    # the definition itself (O(n^2), long double), at the long lengths the
+    # GPU tests feed the oracle
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for sign in (-1, +1):
+        r = rel(oracle.fft1d(x, sign), oracle.dft1d(x, sign))
+        assert r < 1e-14, (n, sign, r)
 
 
 def test_fft1d_rejects_bad_args(oracle):
