@@ -216,6 +216,26 @@ int fft3d_batch_submit_checked(const fft3d_batch_item* items, int n, hipStream_t
  * token or one older than the last 256 ring launches of its device. */
 int fft3d_batch_check(int64_t token);
 
+/* For callers that cannot allocate device or pinned memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fft3d_batch_submit with the task image and counter block of the batched
+ * kernel in a static device array of the library (1 MiB per device, held
+ * until the process ends) instead of the ring.  Allocates nothing: copies the
+ * task image (from a host buffer of the calling thread, pageable) into the
+ * array, clears its counters with a fill kernel, launches, all on `stream`.
+ * Requires fft3d_init on the items' device (which finds the array's address
+ * there).  Items, validation (all or nothing), results (bit-identical to
+ * fft3d_batch_submit's) and the handling of radix-5/7 or odd-n2 items as
+ * fft3d_batch_submit.  Limit: one batched launch of at most 4096 passes
+ * (about 680 ROUNDTRIP items with split planes); a larger batch returns
+ * FFT3D_ERR_UNSUPPORTED and enqueues nothing.  status: NULL, or a device int
+ * that receives the launch's error bits (as fft3d_batch_check: 0 clean, bit 1
+ * a wait hit its spin limit, bit 2 a queue had no workgroup) behind it on the
+ * stream.  Every call on a device shares that device's array: calls on one
+ * device must not overlap in time (issue them on one stream, or order them
+ * with events); overlapping calls race and give wrong results. */
+int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status, hipStream_t stream);
+
 /* A batch built once and launched many times: the task list and its counters
  * live in device memory owned by the handle (allocated here, synchronously),
  * and the launch is a hipGraph of one kernel node (instantiated here) unless

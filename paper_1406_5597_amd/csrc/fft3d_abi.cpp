@@ -607,6 +607,9 @@ int fft3d_init(void)
     if (e != hipSuccess) return hip_fail(e, "fft3d_init: hipGetDevice");
     e = fft3d::ring_init(dev);
     if (e != hipSuccess) return fail(FFT3D_ERR_NOMEM, std::string("fft3d_init: batch ring: ") + hipGetErrorString(e));
+    // the address of this device's copy of the static batch scratch
+    e = fft3d::static_scratch_setup(dev);
+    if (e != hipSuccess) return hip_fail(e, "fft3d_init: static batch scratch");
     return FFT3D_OK;
 }
 
@@ -686,6 +689,65 @@ int fft3d_batch_submit_checked(const fft3d_batch_item* items, int n, hipStream_t
 {
     if (!token) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_batch_submit_checked: token is NULL");
     return batch_submit_impl(items, n, 0, s, token);
+}
+
+int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status, hipStream_t s)
+{
+    const char* who = "fft3d_batch_submit_static";
+    int rc = validate_batch(items, n, who);
+    if (rc) return rc;
+    if (status && ((uintptr_t)status & 3))
+        return fail(FFT3D_ERR_ALIGN, std::string(who) + ": status is not aligned to int");
+    if (n == 0) return FFT3D_OK;
+    std::vector<fft3d_batch_item> even;
+    even.reserve(n);
+    for (int i = 0; i < n; ++i)
+        if (items[i].plan->p.batchable()) even.push_back(items[i]);
+    const int device = items[0].plan->p.device;
+    hipError_t e = hipSuccess;
+    if (!even.empty()) {
+        if (!fft3d::static_scratch(device) || !fft3d::ring_ready(device))
+            return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": fft3d_init() has not been called on device " +
+                                                   std::to_string(device));
+        const fft3d::BatchOptions o = batch_options(device);
+        std::vector<fft3d::BatchSpec> specs = batch_specs(even.data(), (int)even.size());
+        fft3d::BatchTable tab;
+        if (const char* why = fft3d::build_batch_table(specs.data(), (int)even.size(), o, tab))
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
+        const int nt = (int)tab.tasks.size();
+        if (nt > fft3d::kStaticTasks)
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + std::to_string(nt) +
+                                                   " passes, more than the static scratch holds (" +
+                                                   std::to_string(fft3d::kStaticTasks) + ")");
+        const size_t img = fft3d::batch_image_bytes(tab);
+        if (img > fft3d::kStaticCtrOffset)
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": task image larger than the static scratch");
+        unsigned grid = 0;
+        if ((e = fft3d::batch_grid(tab, device, &grid)) != hipSuccess) return hip_fail(e, who);
+        // host staging: this thread's buffer (no device or pinned memory)
+        thread_local std::vector<char> host;
+        host.resize(img);
+        fft3d::write_batch_image(tab, host.data());
+        e = fft3d::launch_static_batch(device, host.data(), img, fft3d::kBatchCtrHeader + nt, grid, tab.lds, status, s);
+        if (e != hipSuccess) return hip_fail(e, who);
+    } else if (status) {
+        // no batched launch: report a clean launch
+        static const int zero = 0;
+        if ((e = hipMemcpyAsync(status, &zero, sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, who);
+    }
+    for (int i = 0; i < n; ++i) {
+        const fft3d_batch_item& it = items[i];
+        if (it.plan->p.batchable()) continue;
+        if (it.dir == FFT3D_R2C) rc = enqueue_r2c(it.plan->p, it.in, it.out, s);
+        else if (it.dir == FFT3D_C2R) rc = enqueue_c2r(it.plan->p, const_cast<void*>(it.in), it.out, it.work, s);
+        else {
+            rc = enqueue_r2c(it.plan->p, it.in, it.mid, s);
+            if (!rc) rc = enqueue_c2r(it.plan->p, it.mid, it.out, it.work, s);
+        }
+        if (rc) return rc;
+    }
+    return FFT3D_OK;
 }
 
 int fft3d_batch_check(int64_t token)

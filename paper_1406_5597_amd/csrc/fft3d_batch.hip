@@ -23,6 +23,8 @@
 // the item run alone.  All tiles are small-tier (the host picks such
 // tilings), which keeps this one kernel -- every tile kind of both dtypes --
 // quick to compile.
+#include <mutex>
+
 #include "fft3d_batch.hpp"
 #include "fft3d_kernels.hpp"
 
@@ -250,6 +252,68 @@ hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, 
 {
     hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(kNtSmall), lds, s, image, ctr, spin_limit);
     return hipGetLastError();
+}
+
+// ---- the allocation-free batched launch ----
+//
+// Callers that cannot allocate (code under graph capture, serving loops that
+// forbid hipMalloc) run a batch through this array: one task image and one
+// counter block per device, held until the process ends.  Every launch on a
+// device shares the device's copy, which keeps the last launch's contents;
+// launches that overlap in time on one device (unordered streams) race.  Host
+// code never passes the array's name to a kernel or a copy (in host code it
+// is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returned on that device.
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kStaticMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_setup(int device)
+{
+    if (device < 0 || device >= kStaticMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (g_static_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the device must be current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_static_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* static_scratch(int device)
+{
+    if (device < 0 || device >= kStaticMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_static_mu);
+    return g_static_ptr[device];
+}
+
+hipError_t launch_static_batch(int device, const void* host_image, size_t bytes, int ctr_ints, unsigned grid,
+                               size_t lds, int* status, hipStream_t s)
+{
+    unsigned char* base = static_cast<unsigned char*>(static_scratch(device));
+    if (!base) return hipErrorNotInitialized;
+    if (bytes > kStaticCtrOffset || ctr_ints < kBatchCtrHeader ||
+        kStaticCtrOffset + (size_t)ctr_ints * sizeof(int) > kStaticScratchBytes)
+        return hipErrorInvalidValue;
+    int* ctr = reinterpret_cast<int*>(base + kStaticCtrOffset);
+    hipError_t e = hipMemcpyAsync(base, host_image, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    // the counters must start at zero: a fill kernel, not a memset node
+    hipLaunchKernelGGL(k_zero_ints<0>, dim3(8), dim3(256), 0, s, ctr, (int64_t)ctr_ints);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_batch(grid, lds, base, ctr, kBatchSpinLimit, s)) != hipSuccess) return e;
+    if (status) e = hipMemcpyAsync(status, ctr + kBatchCtrStatus, sizeof(int), hipMemcpyDeviceToDevice, s);
+    return e;
 }
 
 hipError_t probe_xcc_ids(int blocks, int* ids)

@@ -90,6 +90,17 @@ constexpr int kBatchCtrHeader = kBatchCtrErr + 16;
 constexpr int kBatchErrWait = 1;   // a dependency wait hit its spin limit
 constexpr int kBatchErrQueue = 2;  // a queue's XCD had no workgroup: its items did not run
 
+// Polls of a dependency wait before it gives up (error bit kBatchErrWait).
+constexpr int kBatchSpinLimit = 1 << 20;
+
+// The allocation-free batched launch (fft3d_batch_submit_static) keeps one
+// task image and one counter block per device in a static device array of
+// kStaticScratchBytes: the image at offset 0 (at most kStaticTasks passes,
+// kBatchMaxQueues queues), the counter block at kStaticCtrOffset.
+constexpr int kStaticTasks = 4096;
+constexpr size_t kStaticScratchBytes = (size_t)1 << 20;
+constexpr size_t kStaticCtrOffset = (size_t)768 << 10;
+
 }  // namespace fft3d
 
 #include <hip/hip_runtime_api.h>
@@ -106,5 +117,17 @@ hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, 
 // Hardware XCC id of every workgroup of a `blocks`-block probe launch
 // (synchronous; `ids` gets `blocks` values).
 hipError_t probe_xcc_ids(int blocks, int* ids);
+
+// The static scratch array of fft3d_batch_submit_static.  Setup resolves its
+// address on the current device (once per device; thread-safe); the address
+// is then found by device ordinal (nullptr before setup).
+hipError_t static_scratch_setup(int device);
+void* static_scratch(int device);
+// Copy a task image (host, `bytes` <= kStaticCtrOffset) into the device's
+// scratch, clear the counter block (ctr_ints ints) with a fill kernel, launch
+// the batched kernel on it and, if status is not NULL, copy the launch's
+// error bits to that device int behind it.  All on stream s, no allocation.
+hipError_t launch_static_batch(int device, const void* host_image, size_t bytes, int ctr_ints, unsigned grid,
+                               size_t lds, int* status, hipStream_t s);
 
 }  // namespace fft3d

@@ -44,7 +44,6 @@ struct BatchTable {
     size_t lds = 0;  // dynamic LDS of the launch (largest tile)
 };
 
-constexpr int kBatchSpinLimit = 1 << 20;
 // LDS of one batch tile: half a CU's LDS less the kernel's own (scheduling
 // words and the cached ticket table), so that two workgroups fit on a CU.
 constexpr int64_t kBatchLdsCap = kLdsHalf - 2560;

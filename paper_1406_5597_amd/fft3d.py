@@ -47,7 +47,7 @@ FFT3D_SERVER_MAX_COMP = 8
 
 # Every symbol include/fft3d.h declares.
 EXPORTS = (
-    "fft3d_version", "fft3d_plan", "fft3d_plan_ex", "fft3d_plan_destroy", "fft3d_work_bytes",
+    "fft3d_version", "fft3d_batch_submit_static", "fft3d_plan", "fft3d_plan_ex", "fft3d_plan_destroy", "fft3d_work_bytes",
     "fft3d_real_bytes", "fft3d_complex_bytes", "fft3d_r2c", "fft3d_c2r", "fft3d_batch_submit",
     "fft3d_strerror", "fft3d_last_error", "fft3d_plan_describe", "fft3d_plan_twiddles",
     "fft3d_exchange_block", "fft3d_run_pass", "fft3d_batch_submit_ex", "fft3d_batch_create",
@@ -98,6 +98,7 @@ def _load() -> ctypes.CDLL:
         "fft3d_batch_submit_checked": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp,
                                                       ctypes.POINTER(i64)]),
         "fft3d_batch_check": (ctypes.c_int, [i64]),
+        "fft3d_batch_submit_static": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp, vp]),
         "fft3d_plan": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.POINTER(vp)]),
         "fft3d_plan_ex": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
         "fft3d_plan_destroy": (ctypes.c_int, [vp]),
@@ -330,6 +331,13 @@ def fft3d_batch_submit_checked(items, stream=None) -> int:
     tok = ctypes.c_int64()
     _check(lib.fft3d_batch_submit_checked(_items(items), len(items), _stream(stream), ctypes.byref(tok)))
     return tok.value
+
+
+def fft3d_batch_submit_static(items, status=None, stream=None) -> None:
+    """As fft3d_batch_submit, through the library's static device scratch
+    (no allocation); status: None or a one-int device tensor that receives the
+    launch's error bits."""
+    _check(lib.fft3d_batch_submit_static(_items(items), len(items), _addr(status), _stream(stream)))
 
 
 def fft3d_batch_check(token: int) -> int:
