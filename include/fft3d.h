@@ -89,10 +89,13 @@ enum { FFT3D_R2C = 0, FFT3D_C2R = 1, FFT3D_ROUNDTRIP = 2 };
 /* Plan flags for fft3d_plan_ex. */
 enum {
     FFT3D_PLAN_HOST_ONLY = 1,  /* build schedules/tables on the host only; cannot execute */
-    FFT3D_PLAN_COOP_PLANE = 2  /* planes larger than LDS: one cooperative persistent launch
+    FFT3D_PLAN_COOP_PLANE = 2, /* planes larger than LDS: one cooperative persistent launch
                                   for the plane step (rows + n1 columns through the L2 of
                                   one XCD) instead of the default rows kernel + n1 column
                                   kernel */
+    FFT3D_PLAN_TUNED = 4       /* tile shapes and schedules from the process's tuning table
+                                  (fft3d_autotune, fft3d_tune_load) when it has an entry for
+                                  the shape on this GPU architecture, else the rule */
 };
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -130,6 +133,76 @@ int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out)
  * FFT3D_PLAN_COOP_PLANE selects the cooperative plane step for large planes,
  * which allocates its counter block (some KB) here. */
 int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out);
+
+/* ---- Tuning: the tile shapes and radix schedules of a plan --------------
+ *
+ * How a plan cuts the paper's two steps (Sec. 2.1 items 1 and 3) into kernel
+ * launches: the plane step fused (a whole plane in LDS), split (rows kernel +
+ * n1 column pass) or cooperative (both in one persistent launch through the
+ * L2 of one XCD); the rows per tile of the rows kernels; the width of the
+ * column tiles of the n1 pass and of the strided n0 pass; how n0 tiles are
+ * grouped onto XCDs; the order in which each pass walks its tiles; and the
+ * radix schedule of every axis.  None of this changes what is computed; a
+ * different radix schedule changes the rounding (results stay within the
+ * plan's accuracy bound), the rest gives bit-identical results.
+ *
+ * fft3d_plan picks all of it by rule.  fft3d_plan_tuned takes it from a
+ * tuning (a zero field keeps the rule for that field); fft3d_autotune times
+ * the candidates on the current device and returns the fastest. */
+typedef struct {
+    int32_t plane;       /* 0 rule; FFT3D_TUNE_FUSED, FFT3D_TUNE_SPLIT or FFT3D_TUNE_COOP */
+    int32_t rows_rpw;    /* rows per tile of the rows kernels (split / cooperative plane step) */
+    int32_t n1_w;        /* columns per tile of the n1 pass (power of two, <= 64) */
+    int32_t n0_w;        /* columns per tile of the n0 pass (power of two, <= 64) */
+    int32_t n0_group;    /* n0-pass tiles sent together to one XCD (>= 1) */
+    int32_t walk;        /* 0 rule, else 64 + walk-order bits: a set bit reverses the tile order of
+                            1 rows r2c, 2 n1 forward, 4 n0 forward, 8 n0 inverse, 16 n1 inverse,
+                            32 rows c2r */
+    int32_t coop_lag;    /* cooperative plane step: slots between a plane's two phases (1..256) */
+    int32_t coop_rpw;    /* ... rows per row task */
+    int32_t coop_w;      /* ... columns per column task (power of two) */
+    int32_t radix[3][8]; /* radix schedule of axis 0 (n0), 1 (n1), 2 (the rows: length n2/2 for
+                            even n2, n2 for odd n2), first stage first, 0-terminated; radices 2, 3,
+                            4, 8, 16, 5, 7 with product the axis length; all zero: rule */
+} fft3d_tuning;
+
+enum { FFT3D_TUNE_FUSED = 1, FFT3D_TUNE_SPLIT = 2, FFT3D_TUNE_COOP = 3 };
+
+/* As fft3d_plan_ex with the plan's tile shapes and schedules from *t (NULL:
+ * the rule).  A field that cannot apply to the shape (a fused plane step for
+ * a plane larger than LDS, a tile that fits no kernel tier, a radix list
+ * whose product is not the axis length) is FFT3D_ERR_INVALID_ARG, with the
+ * field named by fft3d_last_error(). */
+int fft3d_plan_tuned(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, const fft3d_tuning* t,
+                     fft3d_plan_t* out);
+
+/* Time the candidate tunings of an n0 x n1 x n2 plan of the given dtype on
+ * the current device and return the fastest in *best (fields the search
+ * left at the rule are 0).  The search, pass by pass with the plan's own
+ * kernels (fft3d_run_pass): rows per rows tile; n1 and n0 tile widths and
+ * the n0 XCD grouping; the radix schedule of every axis; the plane step
+ * (split against cooperative over lags 1..32 and task sizes); the walk
+ * order; then whole r2c+c2r pairs of the rule plan against the tuned one (the
+ * rule is kept unless the tuned plan is faster).  effort 0: a short search;
+ * 1: the full one.  Allocates its own buffers (about 4 x the spectrum's
+ * bytes), synchronises the device, takes seconds.  The winner is also kept in
+ * the process's tuning table (key: GPU architecture, extents, dtype), from
+ * which fft3d_plan_ex with FFT3D_PLAN_TUNED takes it.  report: NULL, or a
+ * buffer for a JSON account of every candidate timed (truncated to len;
+ * the return value is the full length needed, as fft3d_plan_describe). */
+int fft3d_autotune(int64_t n0, int64_t n1, int64_t n2, int dtype, int effort, fft3d_tuning* best, char* report,
+                   size_t len);
+
+/* The tuning table of the process (what fft3d_autotune found, and what
+ * fft3d_tune_load read), keyed by (GPU architecture, n0, n1, n2, dtype).
+ * fft3d_tune_lookup: 1 and *t filled when the current device's architecture
+ * has an entry for the shape, else 0.  fft3d_tune_save writes the table as
+ * JSON to a file; fft3d_tune_load merges a file written so into the table
+ * (entries of the file replace equal keys).  FFT3D_ERR_INVALID_ARG for a
+ * file that cannot be opened or parsed (the table is unchanged then). */
+int fft3d_tune_lookup(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_tuning* t);
+int fft3d_tune_save(const char* path);
+int fft3d_tune_load(const char* path);
 
 /* Free a plan and its device table.  NULL is accepted.  The caller must make
  * sure no enqueued work still uses the plan. */
@@ -260,6 +333,39 @@ int fft3d_batch_status(fft3d_batch_t b);
  * order as [kind, dtype, tiles, index of the task waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
 int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len);
 int fft3d_batch_destroy(fft3d_batch_t b);
+
+/* Launch shape of the batched kernel (what fft3d_batch_autotune chooses;
+ * a zero field keeps the rule):
+ *   mode: 1 pin every item to one XCD (one ticket queue per XCD), 2 one
+ *         queue for all workgroups; rule: pin when that balances the XCDs;
+ *   lag: slots between an item's consecutive passes in the ticket order
+ *        (rule: the number of items, i.e. every item's first pass, then
+ *        every item's second pass, ...);
+ *   widen: 1 small fields get fewer, larger tiles (several planes per plane
+ *          tile, column tiles widened to the tier; the rule), 2 the plans'
+ *          own tile shapes;
+ *   wg_per_cu: workgroups per CU (rule: as many as fit). */
+typedef struct {
+    int32_t mode;
+    int32_t lag;
+    int32_t widen;
+    int32_t wg_per_cu;
+} fft3d_batch_tuning;
+
+/* fft3d_batch_create with a launch shape (bt NULL: the rule).  Out-of-range
+ * fields are FFT3D_ERR_INVALID_ARG. */
+int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, const fft3d_batch_tuning* bt,
+                             fft3d_batch_t* out);
+
+/* Time candidate launch shapes of the batch of these items on the current
+ * device (each as a directly launched batch handle, several launches each)
+ * and return the fastest in *best (the rule is kept unless a candidate is
+ * faster).  The items run many times: their outputs are overwritten, and so
+ * are the inputs of C2R items without work.  Synchronises the device.
+ * report: NULL or a buffer for a JSON account of the candidates (return
+ * value: the full length, as fft3d_plan_describe). */
+int fft3d_batch_autotune(const fft3d_batch_item* items, int n, int effort, fft3d_batch_tuning* best, char* report,
+                         size_t len);
 
 /* The transpose-based method of the paper's Sec. 2.1, for comparison with
  * the transpose-free path (Sec. 2.2): step 1 (the same plane step) into

@@ -44,6 +44,7 @@ SOURCES = [
     ("fft3d_batch_host.cpp", HOST_FLAGS),
     ("fft3d_server.cpp", HOST_FLAGS),
     ("fft3d_plan.cpp", HOST_FLAGS),
+    ("fft3d_tune.cpp", HOST_FLAGS),
     ("fft3d_dispatch.cpp", HOST_FLAGS),
     ("fft3d_abi.cpp", HOST_FLAGS),
 ]

@@ -19,10 +19,6 @@
 #include "fft3d_batch_host.hpp"
 #include "fft3d_internal.hpp"
 
-struct fft3d_plan_s {
-    fft3d::Plan p;
-};
-
 struct fft3d_batch_s {
     int nitems = 0;
     int device = -1;
@@ -142,22 +138,12 @@ int enqueue_r2c(const fft3d::Plan& p, const void* x, void* X, hipStream_t s)
         e = fft3d::launch_plane_coop(p, x, X, false, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_r2c cooperative plane kernel");
     } else {
-        // planes in groups (all at once by default): rows kernel, then the n1
-        // columns of the same planes, walked backwards so the planes the rows
-        // kernel wrote last come first
-        const int64_t G = p.plane_group > 0 ? p.plane_group : p.n0;
-        for (int64_t g0 = 0; g0 < p.n0; g0 += G) {
-            const int64_t gn = std::min(G, p.n0 - g0);
-            const char* xg = static_cast<const char*>(x) + g0 * p.n1 * p.n2 * p.elem;
-            char* Xg = static_cast<char*>(X) + g0 * p.n1 * p.H * 2 * p.elem;
-            e = fft3d::launch_rows_r2c(p, xg, Xg, gn * p.n1, p.rev & 1, s);
-            if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
-            if (p.n1 > 1) {
-                fft3d::ColPass cp = p.pass1;
-                cp.nbatch = gn;
-                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, Xg, Xg, false, (p.rev >> 1) & 1, s);
-                if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
-            }
+        // rows kernel, then the n1 columns of the planes in place
+        e = fft3d::launch_rows_r2c(p, x, X, p.n0 * p.n1, p.rev & 1, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_r2c rows kernel");
+        if (p.n1 > 1) {
+            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, X, X, false, (p.rev >> 1) & 1, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_r2c n1 columns kernel");
         }
     }
     if (p.n0 > 1) {
@@ -193,23 +179,14 @@ int enqueue_c2r(const fft3d::Plan& p, void* X, void* y, void* work, hipStream_t 
         e = fft3d::launch_plane_coop(p, cur, y, true, s);
         if (e != hipSuccess) return hip_fail(e, "fft3d_c2r cooperative plane kernel");
     } else {
-        const int64_t G = p.plane_group > 0 ? p.plane_group : p.n0;
-        for (int64_t g0 = 0; g0 < p.n0; g0 += G) {
-            const int64_t gn = std::min(G, p.n0 - g0);
-            const int64_t off = g0 * p.n1 * p.H * 2 * p.elem;
-            const void* src = static_cast<const char*>(cur) + off;
-            if (p.n1 > 1) {
-                fft3d::ColPass cp = p.pass1;
-                cp.nbatch = gn;
-                void* dst = static_cast<char*>(scratch) + off;
-                e = fft3d::launch_cols(p, cp, 1, p.off_ax1, src, dst, true, (p.rev >> 4) & 1, s);
-                if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
-                src = dst;
-            }
-            char* yg = static_cast<char*>(y) + g0 * p.n1 * p.n2 * p.elem;
-            e = fft3d::launch_rows_c2r(p, src, yg, gn * p.n1, (p.rev >> 5) & 1, s);
-            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
+        const void* src = cur;
+        if (p.n1 > 1) {
+            e = fft3d::launch_cols(p, p.pass1, 1, p.off_ax1, src, scratch, true, (p.rev >> 4) & 1, s);
+            if (e != hipSuccess) return hip_fail(e, "fft3d_c2r n1 columns kernel");
+            src = scratch;
         }
+        e = fft3d::launch_rows_c2r(p, src, y, p.n0 * p.n1, (p.rev >> 5) & 1, s);
+        if (e != hipSuccess) return hip_fail(e, "fft3d_c2r rows kernel");
     }
     return FFT3D_OK;
 }
@@ -316,16 +293,28 @@ std::vector<fft3d::BatchSpec> batch_specs(const fft3d_batch_item* items, int n)
 // order (FFT3D_BATCH_LAG: slots between an item's passes) and of the queue
 // mode (FFT3D_BATCH_MODE: "pinned" or "spread"; default: pinned when that
 // balances the XCDs).
-fft3d::BatchOptions batch_options(int device)
+fft3d::BatchOptions batch_options(int device, const fft3d_batch_tuning* bt = nullptr)
 {
     fft3d::BatchOptions o;
     o.xcc_ids = fft3d::device_xcc_ids(device);
-    if (const char* v = getenv("FFT3D_BATCH_LAG")) o.lag = std::max(0, atoi(v));
-    if (const char* v = getenv("FFT3D_BATCH_MODE")) {
-        if (!strcmp(v, "pinned")) o.mode = 1;
-        else if (!strcmp(v, "spread")) o.mode = 2;
+    if (bt) {
+        o.mode = bt->mode;
+        o.lag = bt->lag;
+        o.widen = bt->widen != 2;
+        o.wg_per_cu = bt->wg_per_cu;
     }
     return o;
+}
+
+int check_batch_tuning(const fft3d_batch_tuning* bt, const char* who)
+{
+    if (!bt) return FFT3D_OK;
+    if (bt->mode < 0 || bt->mode > 2) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": mode must be 0, 1 or 2");
+    if (bt->lag < 0) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": lag must be >= 0");
+    if (bt->widen < 0 || bt->widen > 2) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": widen must be 0, 1 or 2");
+    if (bt->wg_per_cu < 0 || bt->wg_per_cu > 16)
+        return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": wg_per_cu must be 0..16");
+    return FFT3D_OK;
 }
 
 }  // namespace
@@ -338,16 +327,21 @@ extern "C" {
 
 int fft3d_version(void) { return 100; }
 
-int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out)
+int fft3d_plan_tuned(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, const fft3d_tuning* t,
+                     fft3d_plan_t* out)
 {
     if (!out) return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: out is NULL");
     *out = nullptr;
-    if (flags & ~(FFT3D_PLAN_HOST_ONLY | FFT3D_PLAN_COOP_PLANE))
+    if (flags & ~(FFT3D_PLAN_HOST_ONLY | FFT3D_PLAN_COOP_PLANE | FFT3D_PLAN_TUNED))
         return fail(FFT3D_ERR_INVALID_ARG, "fft3d_plan: unknown flags");
+    // FFT3D_PLAN_TUNED: the process's tuning table entry for this shape on
+    // the current device's architecture, if there is one
+    fft3d_tuning looked{};
+    if (!t && (flags & FFT3D_PLAN_TUNED) && fft3d_tune_lookup(n0, n1, n2, dtype, &looked) == 1) t = &looked;
     fft3d_plan_s* h = new (std::nothrow) fft3d_plan_s;
     if (!h) return fail(FFT3D_ERR_NOMEM, "fft3d_plan: out of host memory");
     std::string why;
-    int rc = fft3d::plan_build_host(h->p, n0, n1, n2, dtype, flags, why);
+    int rc = fft3d::plan_build_host(h->p, n0, n1, n2, dtype, flags, t, why);
     if (rc) {
         delete h;
         return fail(rc, "fft3d_plan: " + why);
@@ -412,6 +406,11 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
     }
     *out = h;
     return FFT3D_OK;
+}
+
+int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3d_plan_t* out)
+{
+    return fft3d_plan_tuned(n0, n1, n2, dtype, flags, nullptr, out);
 }
 
 int fft3d_plan(int64_t n0, int64_t n1, int64_t n2, int dtype, fft3d_plan_t* out)
@@ -766,9 +765,16 @@ int fft3d_batch_check(int64_t token)
 
 int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_batch_t* out)
 {
+    return fft3d_batch_create_tuned(items, n, flags, nullptr, out);
+}
+
+int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, const fft3d_batch_tuning* bt,
+                             fft3d_batch_t* out)
+{
     const char* who = "fft3d_batch_create";
     if (!out) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": out is NULL");
     *out = nullptr;
+    if (int rc = check_batch_tuning(bt, who)) return rc;
     if (flags & ~FFT3D_BATCH_DIRECT)
         return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": unknown flags");
     if (n < 1) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": empty batch");
@@ -781,7 +787,7 @@ int fft3d_batch_create(const fft3d_batch_item* items, int n, int flags, fft3d_ba
     if (!fft3d::ring_ready(items[0].plan->p.device))
         return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": fft3d_init() has not been called on device " +
                                                std::to_string(items[0].plan->p.device));
-    fft3d::BatchOptions o = batch_options(items[0].plan->p.device);
+    fft3d::BatchOptions o = batch_options(items[0].plan->p.device, bt);
     std::unique_ptr<fft3d_batch_s> b(new (std::nothrow) fft3d_batch_s);
     if (!b) return fail(FFT3D_ERR_NOMEM, std::string(who) + ": out of host memory");
     b->nitems = n;

@@ -70,15 +70,8 @@ void widen_cols(ColPass& cp, int64_t n, const Plan& p)
     cp.lds = (size_t)(n * cp.W * cxs);
 }
 
-bool batch_widen()
+const char* item_tiling(const Plan& p, bool widen, ItemTiling& t)
 {
-    const char* v = getenv("FFT3D_BATCH_WIDEN");
-    return !v || atoi(v) != 0;
-}
-
-const char* item_tiling(const Plan& p, ItemTiling& t)
-{
-    const bool widen = batch_widen();
     if (p.n0 > 1) {
         t.pass0 = p.pass0;
         if ((t.pass0.big || t.pass0.wide) && !small_colpass(p, 0, t.pass0))
@@ -226,7 +219,7 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
         const BatchSpec& it = items[i];
         const Plan& p = *it.plan;
         ItemTiling pt;
-        if (const char* why = item_tiling(p, pt)) return why;
+        if (const char* why = item_tiling(p, o.widen, pt)) return why;
         std::vector<BatchTask>& c = chains[(size_t)i];
         switch (it.dir) {
         case FFT3D_R2C: chain_r2c(c, p, pt, it.in, it.out); break;
@@ -321,6 +314,7 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
     }
     tab.task_begin[(size_t)nq] = (int)tab.tasks.size();
     tab.lds = lds;
+    tab.wg_per_cu = o.wg_per_cu;
     return nullptr;
 }
 
@@ -362,10 +356,7 @@ hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
     if (e == hipSuccess) e = batch_occupancy(tab.lds, &per_cu);
     if (e != hipSuccess) return e;
     int64_t g = (int64_t)cus * std::max(per_cu, 1);
-    if (const char* v = getenv("FFT3D_BATCH_WG_PER_CU")) {
-        const int w = atoi(v);
-        if (w >= 1 && w <= std::max(per_cu, 1)) g = (int64_t)cus * w;
-    }
+    if (tab.wg_per_cu >= 1 && tab.wg_per_cu <= std::max(per_cu, 1)) g = (int64_t)cus * tab.wg_per_cu;
     // one queue: no more workgroups than tickets; per-XCD queues: every XCD
     // must get workgroups (blocks go to the XCDs in turn), so keep them all
     if (!tab.pinned) g = std::min<int64_t>(g, std::max<int64_t>(tab.tickets, 1));

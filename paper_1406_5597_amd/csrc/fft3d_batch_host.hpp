@@ -28,6 +28,11 @@ struct BatchOptions {
     // slots between an item's consecutive passes in the ticket order; 0 means
     // the number of items (pass-major order)
     int lag = 0;
+    // small fields get fewer, larger tiles (several planes per plane tile,
+    // column tiles widened to the tier); false: the plans' own tile shapes
+    bool widen = true;
+    // workgroups per CU of the launch; 0: as many as fit
+    int wg_per_cu = 0;
 };
 
 struct BatchTable {
@@ -42,6 +47,7 @@ struct BatchTable {
     int qmap[kBatchMaxQueues] = {};
     int64_t tickets = 0;
     size_t lds = 0;  // dynamic LDS of the launch (largest tile)
+    int wg_per_cu = 0;  // workgroups per CU (0: as many as fit)
 };
 
 // LDS of one batch tile: half a CU's LDS less the kernel's own (scheduling

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/fft3d.h"
 #include "fft3d_sched.hpp"
 
 namespace fft3d {
@@ -95,7 +96,6 @@ struct Plan {
     int coop_grid = 0;             // set with the device state
     int coop_nslots = 0;
     int coop_lag = 2;              // slots between a plane's two phases
-    int64_t plane_group = 0;       // split plane step in groups of this many planes (0: all at once)
     int n0_group = 1;              // n0-pass tiles sent together to one XCD (see plan_build_host)
     // Passes that walk their tiles in reverse (each XCD from its last group),
     // one bit per pass: 1 rows r2c, 2 n1 forward, 4 n0 forward, 8 n0 inverse,
@@ -108,6 +108,10 @@ struct Plan {
     int* d_ctr = nullptr;
     AxisSched* d_sched = nullptr;  // device copies of ax0, ax1, ax2h
 
+    // the tuning the plan was built with (fft3d_plan_tuned), if any
+    bool tuned = false;
+    fft3d_tuning tuning{};
+
     // device state
     bool has_device = false;
     int device = -1;
@@ -118,7 +122,8 @@ struct Plan {
 
 // Build the host part of a plan (schedules, tables, strategy).  Returns an
 // FFT3D_* code; `why` receives a message on failure.
-int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why);
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, const fft3d_tuning* t,
+                    std::string& why);
 
 // Tiling of the split plane step (rows kernel + n1 column pass) for the
 // plan's shape and dtype, also for plans that fuse the plane step.  Returns
@@ -131,6 +136,9 @@ bool small_colpass(const Plan& p, int axis, ColPass& cp);
 
 // Factor n = 2^a 3^b 5^c 7^d into stages; false if n has another prime factor.
 bool make_schedule(int64_t n, AxisSched& s);
+// The schedule of an explicit radix list (first stage first); false unless
+// every radix is 2, 3, 4, 8, 16, 5 or 7 and their product is n.
+bool fill_schedule(int64_t n, const int* radices, int cnt, AxisSched& s);
 
 // e^{-2 pi i e/m}, quadrant-reduced, in long double.
 void root_of_unity_ld(int64_t e, int64_t m, long double* c, long double* s);
@@ -209,3 +217,8 @@ hipError_t kernels_init();
 hipError_t coop_setup(Plan& p);
 
 }  // namespace fft3d
+
+// The opaque plan handle of the C interface.
+struct fft3d_plan_s {
+    fft3d::Plan p;
+};

@@ -572,20 +572,25 @@ struct CoopArgs {
     int* ctr;  // [claim][error][ticket x kCoopQueues][queue][slot][plane+1 or -1, done]
 };
 
-__device__ __forceinline__ int coop_wait_nonzero(int* p, int limit)
+// Bounded waits.  Both give up at once when an earlier wait of the launch has
+// already failed (*err != 0), so a failed launch drains in one spin limit
+// instead of one per waiting ticket.
+__device__ __forceinline__ int coop_wait_nonzero(int* p, const int* err, int limit)
 {
     for (int it = 0; it < limit; ++it) {
         const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (v != 0) return v;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
         __builtin_amdgcn_s_sleep(2);
     }
     return 0;
 }
 
-__device__ __forceinline__ bool coop_wait_geq(int* p, int target, int limit)
+__device__ __forceinline__ bool coop_wait_geq(int* p, int target, const int* err, int limit)
 {
     for (int it = 0; it < limit; ++it) {
         if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         __builtin_amdgcn_s_sleep(2);
     }
     return false;
@@ -622,7 +627,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 int* slot = slots + 2 * s;
                 int v;
                 if (k == 0) {
-                    const int prev = s > 0 ? coop_wait_nonzero(slot - 2, a.spin_limit) : 1;
+                    const int prev = s > 0 ? coop_wait_nonzero(slot - 2, a.ctr + 1, a.spin_limit) : 1;
                     if (prev == 0) {
                         atomicOr(&a.ctr[1], 1);
                         v = 0;
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     }
                     if (v != 0) __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
-                    v = coop_wait_nonzero(slot, a.spin_limit);
+                    v = coop_wait_nonzero(slot, a.ctr + 1, a.spin_limit);
                     if (v == 0) atomicOr(&a.ctr[1], 1);
                 }
                 if (v > 0) {
@@ -649,9 +654,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             } else {
                 // second phase of plane P(s - L)
                 int* slot = slots + 2 * (s - a.lag);
-                const int v = coop_wait_nonzero(slot, a.spin_limit);
+                const int v = coop_wait_nonzero(slot, a.ctr + 1, a.spin_limit);
                 if (v > 0) {
-                    if (coop_wait_geq(slot + 1, first, a.spin_limit)) {
+                    if (coop_wait_geq(slot + 1, first, a.ctr + 1, a.spin_limit)) {
                         kind = kCoopTask;
                         pl = v - 1;
                         ps = s - a.lag;

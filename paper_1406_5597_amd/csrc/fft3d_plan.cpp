@@ -64,6 +64,21 @@ bool make_schedule(int64_t n, AxisSched& s)
         if (cnt >= kMaxStages) return false;
         radices[cnt++] = 7;
     }
+    return fill_schedule(n, radices, cnt, s);
+}
+
+bool fill_schedule(int64_t n, const int* radices, int cnt, AxisSched& s)
+{
+    s = AxisSched{};
+    if (n < 1 || n > (int64_t(1) << 30) || cnt < 0 || cnt > kMaxStages) return false;
+    int64_t prod = 1;
+    for (int i = 0; i < cnt; ++i) {
+        const int r = radices[i];
+        if (r != 2 && r != 3 && r != 4 && r != 8 && r != 16 && r != 5 && r != 7) return false;
+        prod *= r;
+    }
+    if (prod != n) return false;
+    s.n = (int32_t)n;
     int32_t ns = 1, off = 0;
     for (int i = 0; i < cnt; ++i) {
         s.radix[i] = radices[i];
@@ -208,6 +223,32 @@ static bool make_colpass(ColPass& cp, int64_t n, int64_t S, int64_t ncols, int64
     return true;
 }
 
+// Set a column pass's tile width to W (a power of two, at most 64): the
+// tier is the smallest that holds n rows of W columns (small, wide, big).
+// False if W is not such a width or no tier holds the tile.
+static bool width_colpass(ColPass& cp, int64_t n, int W, int cxs, int es, int eb)
+{
+    if (W < 1 || W > 64 || (W & (W - 1))) return false;
+    const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
+    const int64_t e = n * W, bytes = e * cxs;
+    bool big = false, wide = false;
+    if (e <= es && bytes <= kLdsHalf) {
+    } else if (e <= ew && bytes <= kLdsMax) {
+        wide = true;
+    } else if (e <= eb && bytes <= kLdsMax) {
+        big = true;
+    } else {
+        return false;
+    }
+    cp.W = W;
+    cp.wshift = ilog2(W);
+    cp.big = big;
+    cp.wide = wide;
+    cp.tiles_per_batch = (cp.ncols + W - 1) / W;
+    cp.lds = (size_t)bytes;
+    return true;
+}
+
 bool small_colpass(const Plan& p, int axis, ColPass& cp)
 {
     const int cxs = 2 * p.elem;
@@ -257,7 +298,8 @@ const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_l
     return nullptr;
 }
 
-int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, std::string& why)
+int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, const fft3d_tuning* t,
+                    std::string& why)
 {
     char msg[256];
     if (n0 < 1 || n1 < 1 || n2 < 1) {
@@ -292,6 +334,27 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         why = msg;
         return FFT3D_ERR_UNSUPPORTED;
     }
+    if (t) {
+        p.tuned = true;
+        p.tuning = *t;
+        AxisSched* axes[3] = {&p.ax0, &p.ax1, &p.ax2h};
+        const int64_t lens[3] = {n0, n1, n2_odd ? n2 : p.h};
+        for (int a = 0; a < 3; ++a) {
+            if (t->radix[a][0] == 0) continue;
+            int cnt = 0;
+            while (cnt < 8 && t->radix[a][cnt] != 0) ++cnt;
+            if (!fill_schedule(lens[a], t->radix[a], cnt, *axes[a])) {
+                snprintf(msg, sizeof msg,
+                         "tuning: radix[%d] is not a schedule of length %lld (radices 2, 3, 4, 8, 16, 5, 7 "
+                         "whose product is the length)",
+                         a, (long long)lens[a]);
+                why = msg;
+                return FFT3D_ERR_INVALID_ARG;
+            }
+        }
+    }
+    const fft3d_tuning tz{};
+    const fft3d_tuning& tu = t ? *t : tz;
 
     for (const AxisSched* a : {&p.ax0, &p.ax1, &p.ax2h})
         for (int i = 0; i < a->nst; ++i)
@@ -336,9 +399,22 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             }
         }
     }
+    if (tu.plane < 0 || tu.plane > FFT3D_TUNE_COOP) {
+        why = "tuning: plane must be 0, FFT3D_TUNE_FUSED, FFT3D_TUNE_SPLIT or FFT3D_TUNE_COOP";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    if (tu.plane == FFT3D_TUNE_FUSED && !fused) {
+        why = "tuning: plane FUSED, but the plane does not fit in LDS (or n2 is odd)";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    if (tu.plane == FFT3D_TUNE_SPLIT || tu.plane == FFT3D_TUNE_COOP) fused = false;
     if (fused) {
         p.fused_plane = true;
         p.ppw = 1;
+        if (tu.rows_rpw || tu.n1_w || tu.coop_lag || tu.coop_rpw || tu.coop_w) {
+            why = "tuning: rows_rpw, n1_w and coop_* apply to split or cooperative plane steps only";
+            return FFT3D_ERR_INVALID_ARG;
+        }
     } else {
         p.fused_plane = false;
         const char* err = split_tiling(p, p.rpw, p.rows_big, p.rows_lds, p.pass1);
@@ -346,52 +422,74 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             why = err;
             return FFT3D_ERR_UNSUPPORTED;
         }
-        // tuning overrides: rows per rows-kernel tile (at most the tier's),
-        // n1-pass tile width (power of two, at most the tier's)
-        if (const char* v = getenv("FFT3D_ROWS_RPW")) {
-            const int r = atoi(v);
-            if (r >= 1 && r < p.rpw && !(n2_odd && (r & 1))) {
-                p.rpw = r;
-                p.rows_lds = (size_t)(p.rpw * p.Hs * cxs);
+        if (tu.rows_rpw) {
+            // up to what the rows kernel's tier holds (the rule keeps an
+            // LDS budget below that, for occupancy)
+            const int r = tu.rows_rpw;
+            const int64_t per_row = (int64_t)p.Hs * cxs;
+            const int64_t emax = p.rows_big ? eb : es, lmax = p.rows_big ? kLdsMax : kLdsHalf;
+            const int64_t rows_cap = n2_odd ? std::min<int64_t>(emax / n2, (int64_t)kNtSmall * kPairItems / p.H) * 2
+                                            : emax / p.h;
+            const int64_t rr = r + (n2_odd ? (r & 1) : 0);
+            if (r < 1 || (n2_odd && (r & 1)) || r > rows_cap || rr * per_row > lmax) {
+                snprintf(msg, sizeof msg, "tuning: rows_rpw %d does not fit the rows kernel (1..%lld%s)", r,
+                         (long long)std::min<int64_t>(rows_cap, lmax / per_row), n2_odd ? ", even" : "");
+                why = msg;
+                return FFT3D_ERR_INVALID_ARG;
             }
+            p.rpw = (int)std::min<int64_t>(r, n0 * n1);
+            p.rows_lds = (size_t)((p.rpw + (n2_odd ? (p.rpw & 1) : 0)) * per_row);
         }
-        if (const char* v = getenv("FFT3D_N1_W")) {
-            const int W = atoi(v);
-            if (W >= 1 && W < p.pass1.W && (W & (W - 1)) == 0) {
-                const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
-                const bool over = n1 * W > es || n1 * W * cxs > kLdsHalf;
-                p.pass1.wide = over && n1 * W <= ew;
-                p.pass1.big = over && !p.pass1.wide;
-                p.pass1.W = W;
-                p.pass1.wshift = ilog2(W);
-                p.pass1.tiles_per_batch = (p.H + W - 1) / W;
-                p.pass1.lds = (size_t)(n1 * W * cxs);
+        if (tu.n1_w) {
+            if (!width_colpass(p.pass1, n1, tu.n1_w, cxs, es, eb)) {
+                snprintf(msg, sizeof msg, "tuning: n1_w %d is not a power of two <= 64 whose tile fits a tier",
+                         tu.n1_w);
+                why = msg;
+                return FFT3D_ERR_INVALID_ARG;
             }
         }
         // one cooperative launch for the plane step when both task kinds fit
-        // the small tier (and the caller did not ask for the two-kernel path)
-        if ((flags & FFT3D_PLAN_COOP_PLANE) && !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1 && !p.odd &&
-            !n2_odd) {
+        // the small tier
+        const bool coop_ok = !p.rows_big && !p.pass1.big && !p.pass1.wide && n1 > 1 && !p.odd && !n2_odd;
+        if (tu.plane == FFT3D_TUNE_COOP && !coop_ok) {
+            why = "tuning: plane COOP needs rows and n1 tiles of the small tier, n1 > 1, even n2 and radix 2/3 "
+                  "schedules";
+            return FFT3D_ERR_INVALID_ARG;
+        }
+        const bool want_coop = tu.plane == FFT3D_TUNE_COOP || (tu.plane == 0 && (flags & FFT3D_PLAN_COOP_PLANE));
+        if (!(want_coop && coop_ok) && (tu.coop_lag || tu.coop_rpw || tu.coop_w)) {
+            why = "tuning: coop_* apply to the cooperative plane step only";
+            return FFT3D_ERR_INVALID_ARG;
+        }
+        if (want_coop && coop_ok) {
             p.coop = true;
             p.coop_rpw = p.rpw;
             p.coop_w = p.pass1.W;
-            // tuning overrides (rows per row task, columns per column task, lag)
-            if (const char* v = getenv("FFT3D_COOP_RPW")) {
-                const int r = atoi(v);
-                if (r >= 1 && r <= p.rpw) p.coop_rpw = r;
+            if (tu.coop_rpw) {
+                if (tu.coop_rpw < 1 || tu.coop_rpw > p.rpw) {
+                    why = "tuning: coop_rpw must be 1..rows per rows tile";
+                    return FFT3D_ERR_INVALID_ARG;
+                }
+                p.coop_rpw = tu.coop_rpw;
             }
-            if (const char* v = getenv("FFT3D_COOP_W")) {
-                const int w = atoi(v);
-                if (w >= 1 && w <= p.pass1.W && (w & (w - 1)) == 0) p.coop_w = w;
+            if (tu.coop_w) {
+                if (tu.coop_w < 1 || tu.coop_w > p.pass1.W || (tu.coop_w & (tu.coop_w - 1))) {
+                    why = "tuning: coop_w must be a power of two up to the n1 tile width";
+                    return FFT3D_ERR_INVALID_ARG;
+                }
+                p.coop_w = tu.coop_w;
             }
-            if (const char* lag = getenv("FFT3D_COOP_LAG")) p.coop_lag = std::max(0, atoi(lag));
+            if (tu.coop_lag) {
+                if (tu.coop_lag < 1 || tu.coop_lag > 256) {
+                    why = "tuning: coop_lag must be 1..256";
+                    return FFT3D_ERR_INVALID_ARG;
+                }
+                p.coop_lag = tu.coop_lag;
+            }
             p.coop_rt = (int)((n1 + p.coop_rpw - 1) / p.coop_rpw);
             p.coop_ct = (int)((p.H + p.coop_w - 1) / p.coop_w);
             p.coop_lds = (size_t)std::max<int64_t>((int64_t)p.coop_rpw * p.Hs * cxs, n1 * p.coop_w * cxs);
         }
-    }
-    if (!p.fused_plane && !p.coop) {
-        if (const char* g = getenv("FFT3D_PLANE_GROUP")) p.plane_group = std::max(0, atoi(g));
     }
     if (!make_colpass(p.pass0, n0, p.C, p.C, 1, 0, cxs, es, eb)) {
         why = "n0 too large for a column tile";
@@ -407,24 +505,25 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     // neighbouring 128-byte segments of every row; keeping 8 (FP32) / 16
     // (FP64) of them on one XCD measured 1.5-3% faster pairs at 512^3
     p.n0_group = dtype == FFT3D_F64 ? 16 : 8;
-    if (const char* g = getenv("FFT3D_N0_GROUP")) p.n0_group = std::max(1, atoi(g));
-    // walk order of each pass (tuning override, bits as Plan::rev)
-    if (const char* r = getenv("FFT3D_REV")) p.rev = atoi(r) & 63;
-    // tuning override of the n0 tile width (power of two; ignored if it does
-    // not fit a tier)
-    if (const char* w = getenv("FFT3D_N0_W")) {
-        ColPass cp = p.pass0;
-        const int W = atoi(w);
-        if (W >= 1 && (W & (W - 1)) == 0 && n0 * W <= eb && n0 * W * cxs <= kLdsMax) {
-            cp.W = W;
-            cp.wshift = ilog2(W);
-            const int64_t ew = (int64_t)es / kNtSmall * kNtWide;
-            const bool over = n0 * W > es || n0 * W * cxs > kLdsHalf;
-            cp.wide = over && n0 * W <= ew;
-            cp.big = over && !cp.wide;
-            cp.tiles_per_batch = (p.C + W - 1) / W;
-            cp.lds = (size_t)(n0 * W * cxs);
-            p.pass0 = cp;
+    if (tu.n0_group) {
+        if (tu.n0_group < 1) {
+            why = "tuning: n0_group must be >= 1";
+            return FFT3D_ERR_INVALID_ARG;
+        }
+        p.n0_group = tu.n0_group;
+    }
+    if (tu.walk) {
+        if (tu.walk < 64 || tu.walk > 127) {
+            why = "tuning: walk must be 0 or 64 + bits (0..63)";
+            return FFT3D_ERR_INVALID_ARG;
+        }
+        p.rev = tu.walk & 63;
+    }
+    if (tu.n0_w) {
+        if (!width_colpass(p.pass0, n0, tu.n0_w, cxs, es, eb)) {
+            snprintf(msg, sizeof msg, "tuning: n0_w %d is not a power of two <= 64 whose tile fits a tier", tu.n0_w);
+            why = msg;
+            return FFT3D_ERR_INVALID_ARG;
         }
     }
     return FFT3D_OK;
@@ -476,9 +575,9 @@ std::string Plan::describe() const
         r += b;
         if (coop) {
             snprintf(b, sizeof b,
-                     "\"coop\": {\"row_tasks\": %d, \"col_tasks\": %d, \"grid\": %d, \"lds\": %zu, "
-                     "\"slots\": %d}, ",
-                     coop_rt, coop_ct, coop_grid, coop_lds, coop_nslots);
+                     "\"coop\": {\"row_tasks\": %d, \"col_tasks\": %d, \"rows_per_task\": %d, "
+                     "\"cols_per_task\": %d, \"lag\": %d, \"grid\": %d, \"lds\": %zu, \"slots\": %d}, ",
+                     coop_rt, coop_ct, coop_rpw, coop_w, coop_lag, coop_grid, coop_lds, coop_nslots);
             r += b;
         }
         r += "\"n1_pass\": " + pass_json(pass1) + "}, ";
@@ -493,7 +592,25 @@ std::string Plan::describe() const
         i += "3, ";
     }
     if (n1_pass) i += "4, ";
-    r += "\"r2c_passes\": " + f + "], \"c2r_passes\": " + i + "5]}";
+    r += "\"r2c_passes\": " + f + "], \"c2r_passes\": " + i + "5], ";
+    // the tuning the plan was built with (fft3d_plan_tuned), or null
+    if (tuned) {
+        char t[256];
+        snprintf(t, sizeof t,
+                 "\"tuning\": {\"plane\": %d, \"rows_rpw\": %d, \"n1_w\": %d, \"n0_w\": %d, \"n0_group\": %d, "
+                 "\"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
+                 tuning.plane, tuning.rows_rpw, tuning.n1_w, tuning.n0_w, tuning.n0_group, tuning.walk,
+                 tuning.coop_lag, tuning.coop_rpw, tuning.coop_w);
+        r += t;
+        for (int a = 0; a < 3; ++a) {
+            r += a ? ", [" : "[";
+            for (int k = 0; k < 8 && tuning.radix[a][k]; ++k) r += (k ? ", " : "") + std::to_string(tuning.radix[a][k]);
+            r += "]";
+        }
+        r += "]}}";
+    } else {
+        r += "\"tuning\": null}";
+    }
     return r;
 }
 

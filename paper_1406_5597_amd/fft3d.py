@@ -30,6 +30,10 @@ FFT3D_C2R = 1
 FFT3D_ROUNDTRIP = 2
 FFT3D_PLAN_HOST_ONLY = 1
 FFT3D_PLAN_COOP_PLANE = 2
+FFT3D_PLAN_TUNED = 4
+FFT3D_TUNE_FUSED = 1
+FFT3D_TUNE_SPLIT = 2
+FFT3D_TUNE_COOP = 3
 FFT3D_PASS_PLANE_R2C = 0
 FFT3D_PASS_N1_FWD = 1
 FFT3D_PASS_N0_FWD = 2
@@ -55,7 +59,8 @@ EXPORTS = (
     "fft3d_server_create", "fft3d_server_submit", "fft3d_server_wait", "fft3d_server_result",
     "fft3d_server_release", "fft3d_server_stats", "fft3d_server_destroy", "fft3d_r2c_transposed",
     "fft3d_c2r_transposed", "fft3d_r2c_pruned", "fft3d_c2r_pruned", "fft3d_r2c_inplace", "fft3d_c2r_inplace",
-    "fft3d_init", "fft3d_batch_submit_checked", "fft3d_batch_check",
+    "fft3d_init", "fft3d_batch_submit_checked", "fft3d_batch_check", "fft3d_plan_tuned", "fft3d_autotune",
+    "fft3d_tune_lookup", "fft3d_tune_save", "fft3d_tune_load", "fft3d_batch_create_tuned", "fft3d_batch_autotune",
 )
 
 
@@ -68,6 +73,41 @@ class Fft3dError(RuntimeError):
 class BatchItem(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("dir", ctypes.c_int), ("in_", ctypes.c_void_p),
                 ("mid", ctypes.c_void_p), ("out", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+TUNING_FIELDS = ("plane", "rows_rpw", "n1_w", "n0_w", "n0_group", "walk", "coop_lag", "coop_rpw", "coop_w")
+
+
+class Tuning(ctypes.Structure):
+    """fft3d_tuning: every field 0 keeps the plan's rule."""
+    _fields_ = [(n, ctypes.c_int32) for n in TUNING_FIELDS] + [("radix", (ctypes.c_int32 * 8) * 3)]
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tuning":
+        t = cls()
+        for k, v in (d or {}).items():
+            if k == "radix":
+                for a, lst in enumerate(v):
+                    for i, r in enumerate(lst):
+                        t.radix[a][i] = int(r)
+            elif k in TUNING_FIELDS:
+                setattr(t, k, int(v))
+            else:
+                raise ValueError("unknown tuning field %r" % k)
+        return t
+
+    def to_dict(self) -> dict:
+        d = {k: int(getattr(self, k)) for k in TUNING_FIELDS}
+        d["radix"] = [[int(r) for r in self.radix[a] if r] for a in range(3)]
+        return d
+
+
+class BatchTuning(ctypes.Structure):
+    """fft3d_batch_tuning: every field 0 keeps the rule."""
+    _fields_ = [(n, ctypes.c_int32) for n in ("mode", "lag", "widen", "wg_per_cu")]
+
+    def to_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k in ("mode", "lag", "widen", "wg_per_cu")}
 
 
 class ServerConfig(ctypes.Structure):
@@ -98,6 +138,17 @@ def _load() -> ctypes.CDLL:
         "fft3d_batch_submit_checked": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp,
                                                       ctypes.POINTER(i64)]),
         "fft3d_batch_check": (ctypes.c_int, [i64]),
+        "fft3d_plan_tuned": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Tuning),
+                                            ctypes.POINTER(vp)]),
+        "fft3d_autotune": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Tuning),
+                                          ctypes.c_char_p, sz]),
+        "fft3d_tune_lookup": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.POINTER(Tuning)]),
+        "fft3d_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+        "fft3d_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+        "fft3d_batch_create_tuned": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int,
+                                                    ctypes.POINTER(BatchTuning), ctypes.POINTER(vp)]),
+        "fft3d_batch_autotune": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(BatchTuning), ctypes.c_char_p, sz]),
         "fft3d_batch_submit_static": (ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int, vp, vp]),
         "fft3d_plan": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.POINTER(vp)]),
         "fft3d_plan_ex": (ctypes.c_int, [i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
@@ -193,15 +244,22 @@ class Plan:
     """An fft3d plan; owns the C handle (destroyed on close / garbage collection)."""
 
     def __init__(self, n0: int, n1: int, n2: int, dtype: str = "f32", host_only: bool = False,
-                 coop_plane: bool = False):
+                 coop_plane: bool = False, tuning=None, tuned: bool = False):
+        """tuning: None (the rule), a dict of fft3d_tuning fields or a Tuning;
+        tuned: take the tuning from the process's tuning table (FFT3D_PLAN_TUNED)."""
         self.shape = (int(n0), int(n1), int(n2))
         self.dtype = dtype
         dt = {"f32": FFT3D_F32, "f64": FFT3D_F64}.get(dtype)
         if dt is None:
             raise ValueError("dtype must be 'f32' or 'f64'")
         h = ctypes.c_void_p()
-        flags = (FFT3D_PLAN_HOST_ONLY if host_only else 0) | (FFT3D_PLAN_COOP_PLANE if coop_plane else 0)
-        _check(lib.fft3d_plan_ex(int(n0), int(n1), int(n2), dt, flags, ctypes.byref(h)))
+        flags = (FFT3D_PLAN_HOST_ONLY if host_only else 0) | (FFT3D_PLAN_COOP_PLANE if coop_plane else 0) | \
+                (FFT3D_PLAN_TUNED if tuned else 0)
+        if tuning is None:
+            _check(lib.fft3d_plan_ex(int(n0), int(n1), int(n2), dt, flags, ctypes.byref(h)))
+        else:
+            t = tuning if isinstance(tuning, Tuning) else Tuning.from_dict(tuning)
+            _check(lib.fft3d_plan_tuned(int(n0), int(n1), int(n2), dt, flags, ctypes.byref(t), ctypes.byref(h)))
         self.handle = h.value
 
     @property
@@ -259,6 +317,52 @@ def fft3d_plan(n0: int, n1: int, n2: int, dtype: str = "f32") -> Plan:
 def fft3d_plan_ex(n0: int, n1: int, n2: int, dtype: str = "f32", flags: int = 0) -> Plan:
     return Plan(n0, n1, n2, dtype, host_only=bool(flags & FFT3D_PLAN_HOST_ONLY),
                 coop_plane=bool(flags & FFT3D_PLAN_COOP_PLANE))
+
+
+def fft3d_plan_tuned(n0: int, n1: int, n2: int, dtype: str = "f32", flags: int = 0, tuning=None) -> Plan:
+    return Plan(n0, n1, n2, dtype, host_only=bool(flags & FFT3D_PLAN_HOST_ONLY),
+                coop_plane=bool(flags & FFT3D_PLAN_COOP_PLANE), tuning=tuning if tuning is not None else {},
+                tuned=bool(flags & FFT3D_PLAN_TUNED))
+
+
+def _dt(dtype: str) -> int:
+    dt = {"f32": FFT3D_F32, "f64": FFT3D_F64}.get(dtype)
+    if dt is None:
+        raise ValueError("dtype must be 'f32' or 'f64'")
+    return dt
+
+
+def fft3d_autotune(n0: int, n1: int, n2: int, dtype: str = "f32", effort: int = 0):
+    """Time candidate tunings on the current device; returns (best tuning as a
+    dict, the JSON report as a dict).  The winner also enters the process's
+    tuning table."""
+    return autotune((n0, n1, n2), dtype, effort)
+
+
+def autotune(shape, dtype: str = "f32", effort: int = 0):
+    """fft3d_autotune with the report: returns (tuning dict, report dict)."""
+    n0, n1, n2 = (int(v) for v in shape)
+    t = Tuning()
+    cap = 1 << 22
+    buf = ctypes.create_string_buffer(cap)
+    n = _check(lib.fft3d_autotune(n0, n1, n2, _dt(dtype), int(effort), ctypes.byref(t), buf, cap))
+    if n >= cap:
+        raise RuntimeError("autotune report larger than %d bytes" % cap)
+    return t.to_dict(), json.loads(buf.value.decode())
+
+
+def fft3d_tune_lookup(n0: int, n1: int, n2: int, dtype: str = "f32"):
+    """The table's tuning for the shape on this device's architecture, or None."""
+    t = Tuning()
+    return t.to_dict() if _check(lib.fft3d_tune_lookup(int(n0), int(n1), int(n2), _dt(dtype), ctypes.byref(t))) else None
+
+
+def fft3d_tune_save(path: str) -> None:
+    _check(lib.fft3d_tune_save(os.fsencode(path)))
+
+
+def fft3d_tune_load(path: str) -> None:
+    _check(lib.fft3d_tune_load(os.fsencode(path)))
 
 
 def fft3d_plan_destroy(plan: Plan) -> None:
@@ -351,10 +455,16 @@ class Batch:
     launched many times; owns the C handle.  Keeps the item tuples (and so the
     plans and tensors) alive as long as it lives."""
 
-    def __init__(self, items, flags: int = 0):
+    def __init__(self, items, flags: int = 0, tuning=None):
+        """tuning: None (the rule), a dict of fft3d_batch_tuning fields or a BatchTuning."""
         self.items = list(items)
         h = ctypes.c_void_p()
-        _check(lib.fft3d_batch_create(_items(self.items), len(self.items), int(flags), ctypes.byref(h)))
+        if tuning is None:
+            _check(lib.fft3d_batch_create(_items(self.items), len(self.items), int(flags), ctypes.byref(h)))
+        else:
+            bt = tuning if isinstance(tuning, BatchTuning) else BatchTuning(**{k: int(v) for k, v in tuning.items()})
+            _check(lib.fft3d_batch_create_tuned(_items(self.items), len(self.items), int(flags), ctypes.byref(bt),
+                                                ctypes.byref(h)))
         self.handle = h.value
 
     def launch(self, stream=None) -> None:
@@ -383,6 +493,22 @@ class Batch:
 
 def fft3d_batch_create(items, flags: int = 0) -> Batch:
     return Batch(items, flags)
+
+
+def fft3d_batch_create_tuned(items, flags: int = 0, tuning=None) -> Batch:
+    return Batch(items, flags, tuning=tuning if tuning is not None else {})
+
+
+def fft3d_batch_autotune(items, effort: int = 0):
+    """Time launch shapes of the batch of these items (their outputs are
+    overwritten); returns (best batch tuning dict, report dict)."""
+    bt = BatchTuning()
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    n = _check(lib.fft3d_batch_autotune(_items(items), len(items), int(effort), ctypes.byref(bt), buf, cap))
+    if n >= cap:
+        raise RuntimeError("batch autotune report larger than %d bytes" % cap)
+    return bt.to_dict(), json.loads(buf.value.decode())
 
 
 def fft3d_batch_launch(batch: Batch, stream=None) -> None:

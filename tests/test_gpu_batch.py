@@ -7,7 +7,6 @@ each output must be bit-identical to the single-item path (fft3d_r2c /
 fft3d_c2r), which the parity tests pin to the FP64 oracle; a sample of items
 is also checked against the oracle directly here.
 """
-import os
 
 import numpy as np
 import pytest
@@ -190,24 +189,33 @@ def test_batch_retiles_big_items_bit_identically(F):
 
 
 @pytest.mark.parametrize("mode", ["pinned", "spread"])
-@pytest.mark.parametrize("lag", ["0", "1", "2", "5"])
+@pytest.mark.parametrize("lag", [0, 1, 2, 5])
 def test_ticket_orders_give_same_bits(F, lag, mode):
     """Other ticket orders (an item's passes `lag` slots apart instead of
     pass-major) and both queue modes (items pinned to XCDs, or one queue for
-    all) change only the schedule, never the bits."""
+    all), set through the batch tuning, change only the schedule, never the
+    bits."""
     mix = fields.batch_mix(12, seed=7)
     say("batch: lag %s mode %s" % (lag, mode))
     items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 5000 + i) for i, (s, d) in enumerate(mix)]
-    os.environ["FFT3D_BATCH_LAG"] = lag
-    os.environ["FFT3D_BATCH_MODE"] = mode
-    try:
-        b = F.Batch([it.tuple() for it in items])
-        assert b.describe()["mode"] == mode
-        b.launch()
-        F.fft3d_batch_submit([it.tuple() for it in items])
-    finally:
-        del os.environ["FFT3D_BATCH_LAG"]
-        del os.environ["FFT3D_BATCH_MODE"]
+    b = F.Batch([it.tuple() for it in items], tuning={"mode": 1 if mode == "pinned" else 2, "lag": lag})
+    assert b.describe()["mode"] == mode
+    b.launch()
+    _sync()
+    for it in items:
+        it.check_bits()
+    assert b.status() == 0
+
+
+@pytest.mark.parametrize("widen,wg", [(2, 0), (1, 1), (2, 1)])
+def test_batch_tile_shapes_give_same_bits(F, widen, wg):
+    """The plans' own tile shapes instead of widened ones, and one workgroup
+    per CU: same bits."""
+    mix = fields.batch_mix(10, seed=17)
+    say("batch: widen %d wg_per_cu %d" % (widen, wg))
+    items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 5500 + i) for i, (s, d) in enumerate(mix)]
+    b = F.Batch([it.tuple() for it in items], flags=F.FFT3D_BATCH_DIRECT, tuning={"widen": widen, "wg_per_cu": wg})
+    b.launch()
     _sync()
     for it in items:
         it.check_bits()
