@@ -126,7 +126,7 @@ int main(int argc, char** argv)
         if (sscanf(line, "%lld %lld %lld %d %d %d", &n0, &n1, &n2, &dt, &dir, &work) != 6) continue;
         Plan p;
         std::string why;
-        if (plan_build_host(p, n0, n1, n2, dt, 0, why)) return fail("plan: " + why);
+        if (plan_build_host(p, n0, n1, n2, dt, 0, nullptr, why)) return fail("plan: " + why);
         plans.push_back(p);
         dirs.push_back(dir);
         works.push_back(work);
