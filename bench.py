@@ -64,11 +64,42 @@ def pair_bytes_min(shape, elem: int) -> int:
     return 2 * (elem * N + 2 * elem * M)
 
 
-def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=False):
-    plan = F.Plan(*shape, dtype=dtype, coop_plane=coop_plane)
+# The paper's steps (Sec. 2.1 items 1 and 3, and their inverses) and the
+# kernels that make them up; B_alg counts each step as one read and one write
+# of the array (steps_alg_bytes), the split plane step spends two sweeps on it.
+STEPS = (("a2_plane_r2c", (0, 1)), ("a3_n0_fwd", (2,)), ("a4_n0_inv", (3,)), ("a5_plane_c2r", (4, 5)))
+
+
+def step_alg_bytes(step: str, shape, elem: int) -> int:
+    n0, n1, n2 = shape
+    N = n0 * n1 * n2
+    M = n0 * n1 * (n2 // 2 + 1)
+    if step in ("a2_plane_r2c", "a5_plane_c2r"):
+        return elem * N + 2 * elem * M
+    return 4 * elem * M
+
+
+def pair_timer(torch, fn, steps, warmup, s):
+    """ms per call of fn on stream s: warm-up, then `steps` calls between two
+    events."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=False, tuned=False, x_dev=None):
+    plan = F.Plan(*shape, dtype=dtype, coop_plane=coop_plane, tuned=tuned)
     desc = plan.describe()
     elem = 4 if dtype == "f32" else 8
-    x = torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
+    x = x_dev if x_dev is not None else torch.from_numpy(fields.as_dtype(x64, dtype)).to("cuda")
     X = F.empty_complex(plan)
     y = F.empty_real(plan)
     work = F.empty_complex(plan)
@@ -129,8 +160,22 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
     for p, t in tot.items():
         avg_ms = t / steps
         gbs = pass_bytes(p, shape, elem) / (avg_ms * 1e-3) / 1e9
-        kern[PASS_NAMES[p]] = {"avg_us": round(avg_ms * 1e3, 2), "alg_bytes": pass_bytes(p, shape, elem),
+        # the kernel's own read + write bytes; for the plane and n0 kernels
+        # these are the step's algorithmic bytes, the n1 passes are the extra
+        # sweep of the split plane step (not in B_alg)
+        kern[PASS_NAMES[p]] = {"avg_us": round(avg_ms * 1e3, 2), "swept_bytes": pass_bytes(p, shape, elem),
+                               "bytes_are": "swept (extra sweep, not in B_alg)" if p in (1, 4) else "alg",
                                "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # step level: the kernels of each of the paper's steps against its B_alg
+    steps_tab = {}
+    for name, pids in STEPS:
+        us = sum(tot[p] / steps * 1e3 for p in pids if p in tot)
+        if us <= 0:
+            continue
+        ab = step_alg_bytes(name, shape, elem)
+        steps_tab[name] = {"kernels": [PASS_NAMES[p] for p in pids if p in tot], "us": round(us, 2),
+                           "alg_bytes": ab, "GB_s_alg": round(ab / (us * 1e-6) / 1e9, 1),
+                           "frac_alg": round(ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     dom = max(tot, key=lambda p: tot[p])
     n = shape[0] * shape[1] * shape[2]
     flops_pair = 2 * 5 * n * math.log2(n)
@@ -146,19 +191,62 @@ def run_dtype(F, torch, x64, shape, dtype, steps, warmup, fields, coop_plane=Fal
         "gflops": flops_pair / (ms * 1e-3) / 1e9,
         "B_alg_per_pair": b_alg,
         "kernels": kern,
+        "steps": steps_tab,
         "dominant": PASS_NAMES[dom],
         "roofline": {"bound": "hbm", "achieved": kern[PASS_NAMES[dom]]["GB_s"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kern[PASS_NAMES[dom]]["frac"], "traffic": None,
                      "kernel": PASS_NAMES[dom], "alg_bytes_per_launch": pass_bytes(dom, shape, elem),
                      "avg_us": kern[PASS_NAMES[dom]]["avg_us"]},
         "plan": {"plane": desc["plane"]["kind"], "n0_W": desc["n0_pass"]["W"],
-                 "coop": desc["plane"].get("coop")},
+                 "coop": desc["plane"].get("coop"), "tuning": desc.get("tuning")},
     }
     # one more pair for the accuracy check against the oracle sample
     pair()
     torch.cuda.synchronize()
     res = (plan, x, X, y)
     return out, res
+
+
+def run_size(F, torch, shape, dtype, x, steps, warmup, traffic, note):
+    """pairs/s of one more (shape, dtype): the tuned plan (the rule unless the
+    tuning table has this shape), x resident on the device.  Fractions of the
+    HBM peak by B_alg, B_min, the split path's swept bytes and, when a counter
+    record of the current sources exists for this configuration, the
+    measured bytes."""
+    plan = F.Plan(*shape, dtype=dtype, tuned=True)
+    X = F.empty_complex(plan)
+    y = F.empty_real(plan)
+    work = F.empty_complex(plan)
+    s = torch.cuda.current_stream()
+
+    def pair():
+        F.fft3d_r2c(plan, x, X, s)
+        F.fft3d_c2r(plan, X, y, work, s)
+
+    ms = pair_timer(torch, pair, steps, warmup, s)
+    elem = 4 if dtype == "f32" else 8
+    n = shape[0] * shape[1] * shape[2]
+    out = {"shape": list(shape), "dtype": dtype, "note": note, "pairs_s": round(1e3 / ms, 2),
+           "ms_per_pair": round(ms, 4), "plane": plan.describe()["plane"]["kind"],
+           "gflops": round(2 * 5 * n * math.log2(n) / (ms * 1e-3) / 1e9, 1)}
+    for key, b in (("alg", pair_bytes_alg(shape, elem)), ("min", pair_bytes_min(shape, elem)),
+                   ("swept", pair_bytes_swept(shape, elem))):
+        out["B_" + key] = b
+        out["hbm_frac_" + key] = round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    meas = measured_pair_bytes(traffic, shape, dtype)
+    out["B_meas"] = meas
+    out["hbm_frac_meas"] = round(meas / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if meas else None
+    del X, y, work
+    return out
+
+
+def measured_pair_bytes(traffic, shape, dtype):
+    """Counter bytes (fetch + write, calibrated) of one pair's kernels, from
+    the committed counter record of the current sources, or None."""
+    rec = ((traffic or {}).get("configs") or {}).get("x".join(map(str, shape)), {}).get(dtype)
+    if not rec:
+        return None
+    return int(sum(k["fetch_bytes"] + k["write_bytes"] for k in rec.values()))
 
 
 def run_ablation(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
@@ -282,7 +370,9 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times one
     persistent launch of the whole batch (graph replay of a batch handle, and
     the ring-staged fft3d_batch_submit) against the same items launched field
-    by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL)."""
+    by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL), and the launch
+    shape the batch autotuner picks.  Returns (one item per (shape, dtype)
+    with the outputs of the last launch, the record)."""
     mix = fields.batch_mix(count, seed)
     plans, items = {}, []
     b_alg = 0
@@ -327,8 +417,36 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     ms_seq = timed(lambda: F.fft3d_batch_submit_ex(items, F.FFT3D_BATCH_SEQUENTIAL, s))
     status = handle.status()
     desc = handle.describe()
+    # the batch autotuner's launch shape, as a graph-launched handle
+    bt, rep = F.fft3d_batch_autotune(items, effort=0)
+    tuned_handle = F.Batch(items, tuning=bt)
+    ms_tuned = timed(lambda: tuned_handle.launch(s))
+    status_tuned = tuned_handle.status()
+    # the outputs of the last launch: FP32 items against the plain FP64 path
+    # on the same GPU (the FP32 input upcast), one item per shape
+    fp64_cmp, seen = {}, set()
+    for i, (shape, dt) in enumerate(mix):
+        if dt != "f32" or shape in seen:
+            continue
+        seen.add(shape)
+        p, _, x, mid, out, w = items[i]
+        p64 = F.Plan(*shape, dtype="f64")
+        X64 = F.r2c(p64, x.double())
+        y64 = F.c2r(p64, X64.clone(), work=F.empty_complex(p64))
+        torch.cuda.synchronize()
+        fp64_cmp["x".join(map(str, shape))] = {
+            "rel_l2_r2c": float(torch.linalg.vector_norm((mid.to(torch.complex128) - X64).ravel()) /
+                                torch.linalg.vector_norm(X64.ravel())),
+            "rel_l2_c2r": float(torch.linalg.vector_norm((out.double() - y64).ravel()) /
+                                torch.linalg.vector_norm(y64.ravel()))}
     gbs = b_alg / (ms_graph * 1e-3) / 1e9
-    return {
+    samples = []
+    seen = set()
+    for i, (shape, dt) in enumerate(mix):
+        if (shape, dt) not in seen:
+            seen.add((shape, dt))
+            samples.append((shape, dt, items[i]))
+    return samples, {
         "workload": "%d fields (seed %d) of %s, FP32/FP64 mixed (%d FP64), %.1f M real points, ROUNDTRIP "
                     "items" % (count, seed, "/".join("x".join(map(str, sh)) for sh in fields.BATCH_SHAPES),
                                sum(d == "f64" for _, d in mix), points / 1e6),
@@ -342,7 +460,13 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
         "hbm_frac_alg": round(gbs / HBM_PEAK_GBS, 4),
         "grid": desc["grid"], "tickets": desc["tickets"], "tasks": len(desc["tasks"]), "lds": desc["lds"],
         "status": status,
+        "tuned": {"batch_tuning": bt, "ms_per_launch": round(ms_tuned, 4), "fields_s": round(count * 1e3 / ms_tuned, 1),
+                  "GB_s_alg": round(b_alg / (ms_tuned * 1e-3) / 1e9, 1), "speedup_vs_rule": round(ms_graph / ms_tuned, 3),
+                  "status": status_tuned, "candidates": len(rep["candidates"])},
+        "f32_vs_plain_f64_gpu": fp64_cmp,
     }
+    # (samples: one item per (shape, dtype) with the outputs of the last
+    # launch, for the oracle leg)
 
 
 def served_bytes_alg(shape, dtype, direction, ncomp=3) -> int:
@@ -458,6 +582,54 @@ def run_served(F, torch, fields, rate=200.0, measured=2000, warmup_s=5.0, seed=5
     }
 
 
+def served_samples(F, torch, fields, budget=16 * 10**9):
+    """A few requests through a server (both directions, both dtypes, shapes
+    up to 128^3) with inputs from the numpy generators, so that the oracle
+    leg can check them; FP32 ones are also compared with the plain FP64 path
+    on the same GPU.  Returns (records, host data for the oracle leg)."""
+    import numpy as np
+    cases = [((64, 64, 64), "f32"), ((64, 64, 64), "f64"), ((128, 128, 128), "f32"), ((96, 96, 96), "f64")]
+    srv = F.Server(budget, nstreams=2)
+    recs, host = [], []
+    try:
+        for k, (shape, dt) in enumerate(cases):
+            for direction in (0, 1):
+                seed = 2500 + 2 * k + direction
+                if direction == 0:
+                    inp = fields.as_dtype(fields.velocity_field(shape, seed), dt)
+                else:
+                    inp = fields.as_dtype(fields.velocity_spectrum(shape, seed), dt)
+                dev = [torch.from_numpy(np.ascontiguousarray(inp[c])).to("cuda") for c in range(3)]
+                rid = srv.submit(shape, dt, direction, dev)
+                srv.wait(rid, 120.0)
+                addrs, _ = srv.result(rid, 3)
+                rdt, cdt = F.torch_dtypes(dt)
+                n0, n1, n2 = shape
+                oshape, odt = ((n0, n1, n2 // 2 + 1), cdt) if direction == 0 else ((n0, n1, n2), rdt)
+                outs = []
+                for c in range(3):
+                    t = torch.empty(oshape, dtype=odt, device="cuda")
+                    F.copy_from_device(t, addrs[c], t.numel() * t.element_size())
+                    outs.append(t.cpu().numpy())
+                srv.release(rid)
+                rec = {"shape": list(shape), "dtype": dt, "dir": "r2c" if direction == 0 else "c2r"}
+                if dt == "f32":
+                    p64 = F.Plan(*shape, dtype="f64")
+                    errs = []
+                    for c in range(3):
+                        a = dev[c].to(torch.complex128 if direction else torch.float64)
+                        ref = F.r2c(p64, a) if direction == 0 else F.c2r(p64, a.clone(), work=F.empty_complex(p64))
+                        torch.cuda.synchronize()
+                        r = ref.cpu().numpy()
+                        errs.append(float(np.linalg.norm((outs[c].astype(r.dtype) - r).ravel()) / np.linalg.norm(r.ravel())))
+                    rec["rel_l2_vs_plain_f64_gpu"] = max(errs)
+                recs.append(rec)
+                host.append((shape, dt, direction, inp, outs))
+    finally:
+        srv.close()
+    return recs, host
+
+
 def kernel_source_sha256() -> str:
     """Hash of the HIP/C++ sources of the library: a traffic figure measured on
     other sources is stale."""
@@ -475,7 +647,7 @@ def recorded_traffic():
     """Per-kernel HBM bytes (FETCH_SIZE and WRITE_SIZE, scaled by the copy
     calibration) from the committed rocprofv3 summary, if it was taken on the
     current sources; else None."""
-    path = os.path.join(ROOT, "profiles", "fft3d_512cubed_traffic.md")
+    path = os.path.join(ROOT, "profiles", "fft3d_pair_traffic.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -517,6 +689,8 @@ def main() -> int:
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s) of the served stream")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per served rate")
     ap.add_argument("--serve-warmup", type=float, default=10.0, help="seconds of unmeasured arrivals first")
+    ap.add_argument("--no-tune", action="store_true", help="time the rule plans only (no autotuner run)")
+    ap.add_argument("--no-sizes", action="store_true", help="skip the 256^3 FP64 and 1024^3 lines")
     ap.add_argument("--coop-plane", action="store_true",
                     help="cooperative one-launch plane step for large planes instead of the two kernels")
     args = ap.parse_args()
@@ -538,14 +712,73 @@ def main() -> int:
     x64 = fields.k53_field(shape, seed=3)
     print("# field %s generated in %.1f s" % (shape, time.time() - t0), file=sys.stderr, flush=True)
     dtypes = [d for d in args.dtypes.split(",") if d]
-    results, keep = {}, {}
+    traffic = recorded_traffic()
+    results, keep, tune = {}, {}, {}
     for d in dtypes:
+        tuned = not args.coop_plane and not args.no_tune
+        if tuned:
+            # the autotuner first (its winner enters the tuning table; the
+            # rule is kept unless a candidate is faster)
+            t0 = time.time()
+            best, rep = F.autotune(shape, d, effort=0)
+            tune[d] = {"tuning": best, "kept": rep["kept"], "search_s": round(time.time() - t0, 2),
+                       "candidates": len(rep["candidates"]), "pair_ms_rule": rep["pair_ms_rule"],
+                       "pair_ms_tuned": rep["pair_ms_tuned"]}
+            print("# autotune %s: kept %s (%s), %.1f s" % (d, rep["kept"], best, time.time() - t0),
+                  file=sys.stderr, flush=True)
         print("# timing %s ..." % d, file=sys.stderr, flush=True)
         results[d], keep[d] = run_dtype(F, torch, x64, shape, d, args.steps, args.warmup, fields,
-                                        args.coop_plane)
+                                        args.coop_plane, tuned=tuned)
+        if tuned:
+            # the rule plan on the same input, for comparison
+            rp = F.Plan(*shape, dtype=d)
+            plan_t, xt, Xt_, yt = keep[d]
+            wt = F.empty_complex(rp)
+            st = torch.cuda.current_stream()
+            ms_rule = pair_timer(torch, lambda: (F.fft3d_r2c(rp, xt, Xt_, st), F.fft3d_c2r(rp, Xt_, yt, wt, st)),
+                                 args.steps, args.warmup, st)
+            # leave the tuned plan's last pair in X and y for the accuracy check
+            F.fft3d_r2c(plan_t, xt, Xt_, st)
+            F.fft3d_c2r(plan_t, Xt_, yt, wt, st)
+            torch.cuda.synchronize()
+            del wt, rp
+            tune[d]["bench_ms_rule"] = round(ms_rule, 4)
+            tune[d]["bench_ms_tuned"] = round(results[d]["ms_per_pair"], 4)
+            tune[d]["speedup_vs_rule"] = round(ms_rule / results[d]["ms_per_pair"], 4)
         print("# %s: %.3f ms/pair, %.1f pairs/s, dominant %s %.1f GB/s" % (
             d, results[d]["ms_per_pair"], results[d]["pairs_s"], results[d]["dominant"],
             results[d]["roofline"]["achieved"]), file=sys.stderr, flush=True)
+    sizes = None
+    if not args.no_sizes:
+        sizes = []
+        # 256^3 FP64 (k^-5/3 field, |k| <= 85, seed 2): its working set is
+        # about the size of the 256 MB memory-side cache (cache-assisted)
+        s3 = (256, 256, 256)
+        x256 = torch.from_numpy(fields.k53_field(s3, seed=2, kmax=85)).to("cuda")
+        if not args.no_tune:
+            F.autotune(s3, "f64", effort=0)
+        sizes.append(run_size(F, torch, s3, "f64", x256, args.steps, args.warmup, traffic,
+                              "k^-5/3 field |k|<=85 seed 2; working set ~ the 256 MB memory-side cache: "
+                              "cache-assisted"))
+        del x256
+        # 1024^3: a uniform[-1,1] field made on the device (torch generator,
+        # seed 3); the pair's time does not depend on the values (the parity
+        # tests compare the 1024^3 k^-5/3 outputs with the oracle)
+        s4 = (1024, 1024, 1024)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        for d in dtypes:
+            rdt = torch.float32 if d == "f32" else torch.float64
+            xb = torch.rand(s4, generator=g, device="cuda", dtype=rdt) * 2 - 1
+            if not args.no_tune:
+                F.autotune(s4, d, effort=0)
+            sizes.append(run_size(F, torch, s4, d, xb, max(5, args.steps // 5), min(args.warmup, 3), traffic,
+                                  "uniform[-1,1] made on the device (torch seed 3)"))
+            del xb
+            torch.cuda.empty_cache()
+        for z in sizes:
+            print("# size %s %s: %.2f pairs/s (%.1f%% of peak by B_alg)" % (
+                z["shape"], z["dtype"], z["pairs_s"], 100 * z["hbm_frac_alg"]), file=sys.stderr, flush=True)
     ablation = None
     if not args.no_ablation:
         ablation = {}
@@ -570,13 +803,16 @@ def main() -> int:
     batch = None
     if not args.no_batch:
         print("# mixed batch ...", file=sys.stderr, flush=True)
-        batch = run_batch(F, torch, fields, args.steps, args.warmup)
+        batch_samples, batch = run_batch(F, torch, fields, args.steps, args.warmup)
         print("# batch: %.3f ms/launch (%.1f fields/s, %.1f GB/s), per-field launches %.3f ms" % (
             batch["ms_per_launch"], batch["fields_s"], batch["GB_s_alg"], batch["ms_per_field_launches"]),
             file=sys.stderr, flush=True)
 
     served = None
+    served_acc, served_host = None, None
     if not args.no_serve:
+        print("# served samples ...", file=sys.stderr, flush=True)
+        served_acc, served_host = served_samples(F, torch, fields)
         served = []
         for rate in [float(v) for v in args.serve_rates.split(",") if v]:
             print("# served stream at %.0f req/s ..." % rate, file=sys.stderr, flush=True)
@@ -613,6 +849,37 @@ def main() -> int:
             results[d]["rel_l2_r2c"] = fields.rel_l2(Xd.cpu().numpy(), Xo)
             results[d]["rel_l2_c2r"] = fields.rel_l2(yd.cpu().numpy(), yo)
         del Xo, yo
+        # every other dtype: one oracle pair on its own input
+        for d in dtypes:
+            if d == head:
+                continue
+            p, xd, Xd, yd = keep[d]
+            xin_d = fields.as_dtype(x64, d).astype(np.float64)
+            Xo = oracle.r2c(xin_d)
+            yo = oracle.c2r(Xo, n)
+            results[d]["rel_l2_r2c"] = fields.rel_l2(Xd.cpu().numpy(), Xo)
+            results[d]["rel_l2_c2r"] = fields.rel_l2(yd.cpu().numpy(), yo)
+            del Xo, yo
+        # the batch: one item per (shape, dtype), outputs of the last launch
+        if batch is not None:
+            acc = {}
+            for shp, dt_, it in batch_samples:
+                p, _, xb, mid, out, w = it
+                xin_b = xb.cpu().numpy().astype(np.float64)
+                Xo = oracle.r2c(xin_b)
+                yo = oracle.c2r(Xo, shp[2])
+                acc["%s_%s" % ("x".join(map(str, shp)), dt_)] = {
+                    "rel_l2_r2c": fields.rel_l2(mid.cpu().numpy(), Xo), "rel_l2_c2r": fields.rel_l2(out.cpu().numpy(), yo)}
+            batch["rel_l2_vs_oracle"] = acc
+        # served samples: every component of each request
+        if served_host is not None:
+            for rec, (shp, dt_, direction, inp, outs) in zip(served_acc, served_host):
+                errs = []
+                for c in range(3):
+                    a = inp[c].astype(np.complex128 if direction else np.float64)
+                    ref = oracle.r2c(a) if direction == 0 else oracle.c2r(a, shp[2])
+                    errs.append(fields.rel_l2(outs[c], ref))
+                rec["rel_l2_vs_oracle"] = max(errs)
         # smaller configurations, one thread and all threads (seconds per pair)
         small = {}
         for m in (32, 256):
@@ -630,14 +897,20 @@ def main() -> int:
                              round(1.0 / cpu["value"], 3)}
         cpu["pair_seconds_fp64"] = small
 
-    traffic = recorded_traffic()
     for d in dtypes:
         roof = results[d]["roofline"]
-        t = (traffic or {}).get(d, {}).get(roof["kernel"])
-        if t and shape == (512, 512, 512):
+        rec = ((traffic or {}).get("configs") or {}).get("x".join(map(str, shape)), {}).get(d, {})
+        t = rec.get(roof["kernel"])
+        if t:
             roof["traffic"] = int(t["fetch_bytes"] + t["write_bytes"])
             roof["traffic_fetch"] = int(t["fetch_bytes"])
             roof["traffic_write"] = int(t["write_bytes"])
+        meas = measured_pair_bytes(traffic, shape, d)
+        elem = 4 if d == "f32" else 8
+        ms = results[d]["ms_per_pair"]
+        results[d]["hbm_frac_swept"] = pair_bytes_swept(shape, elem) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        results[d]["B_meas_per_pair"] = meas
+        results[d]["hbm_frac_meas"] = meas / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS if meas else None
     head = dtypes[0]
     r = results[head]
     line = {
@@ -660,8 +933,13 @@ def main() -> int:
                    "shape": list(shape), "parallelism": "single GPU"},
         "hbm_frac_alg": round(r["hbm_frac_alg"], 4),
         "hbm_frac_min": round(r["hbm_frac_min"], 4),
+        "hbm_frac_swept": round(r["hbm_frac_swept"], 4),
+        "hbm_frac_meas": None if r["hbm_frac_meas"] is None else round(r["hbm_frac_meas"], 4),
+        "B_alg_per_pair": r["B_alg_per_pair"],
+        "B_meas_per_pair": r["B_meas_per_pair"],
         "GB_s_alg": round(r["GB_s_alg"], 1),
         "gflops": round(r["gflops"], 1),
+        "paper_steps": r["steps"],
         "kernels": r["kernels"],
         "roofline": r["roofline"],
         "plan": r["plan"],
@@ -671,6 +949,9 @@ def main() -> int:
         "served": served,
         "ablation_transpose": ablation,
         "pruned_two_thirds": pruned,
+        "autotune": tune or None,
+        "sizes": sizes,
+        "served_samples": served_acc,
     }
     for k in ("rel_l2_r2c", "rel_l2_c2r"):
         if k in r:
@@ -680,7 +961,14 @@ def main() -> int:
         line[d] = {"value": round(o["pairs_s"], 2), "unit": "pairs/s", "ms_per_step": round(o["ms_per_pair"], 4),
                    "pair_ms_p10_p50_p90": o["pair_ms_p10_p50_p90"],
                    "hbm_frac_alg": round(o["hbm_frac_alg"], 4), "hbm_frac_min": round(o["hbm_frac_min"], 4),
-                   "gflops": round(o["gflops"], 1), "kernels": o["kernels"], "roofline": o["roofline"]}
+                   "hbm_frac_swept": round(o["hbm_frac_swept"], 4),
+                   "hbm_frac_meas": None if o["hbm_frac_meas"] is None else round(o["hbm_frac_meas"], 4),
+                   "B_alg_per_pair": o["B_alg_per_pair"], "B_meas_per_pair": o["B_meas_per_pair"],
+                   "gflops": round(o["gflops"], 1), "paper_steps": o["steps"], "kernels": o["kernels"],
+                   "roofline": o["roofline"], "plan": o["plan"]}
+        for k in ("rel_l2_r2c", "rel_l2_c2r"):
+            if k in o:
+                line[d][k] = o[k]
     print(json.dumps(line), flush=True)
     return 0
 
