@@ -630,16 +630,30 @@ def served_samples(F, torch, fields, budget=16 * 10**9):
     return recs, host
 
 
+# The configurations whose counter bytes profiles/fft3d_pair_traffic.md records.
+TRAFFIC_CONFIGS = (((512, 512, 512), "f32"), ((512, 512, 512), "f64"), ((256, 256, 256), "f64"),
+                   ((1024, 1024, 1024), "f32"), ((1024, 1024, 1024), "f64"))
+DEVICE_SOURCES = ("fft3d_kernels.hpp", "fft3d_device.hpp", "fft3d_pruned.hpp", "fft3d_sched.hpp", "fft3d_batch.hpp",
+                  "fft3d_internal.hpp")
+
+
 def kernel_source_sha256() -> str:
-    """Hash of the HIP/C++ sources of the library: a traffic figure measured on
-    other sources is stale."""
+    """Identity of what the counters measured: the device code (every .hip
+    file and the headers it includes) and the launch shapes of the rule plans
+    of the recorded configurations (their descriptions).  A counter record
+    taken on another identity is stale."""
     import hashlib
+    from paper_1406_5597_amd import fft3d as F
     d = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith(".hip") or name in DEVICE_SOURCES:
             h.update(name.encode())
             h.update(open(os.path.join(d, name), "rb").read())
+    for shape, dt in TRAFFIC_CONFIGS:
+        desc = F.Plan(*shape, dtype=dt, host_only=True).describe()
+        desc.pop("device", None)
+        h.update(json.dumps(desc, sort_keys=True).encode())
     return h.hexdigest()
 
 

@@ -9,6 +9,7 @@
 // This plain struct is shared by the host builder and the kernel.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "fft3d_sched.hpp"

@@ -430,7 +430,7 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             const int64_t emax = p.rows_big ? eb : es, lmax = p.rows_big ? kLdsMax : kLdsHalf;
             const int64_t rows_cap = n2_odd ? std::min<int64_t>(emax / n2, (int64_t)kNtSmall * kPairItems / p.H) * 2
                                             : emax / p.h;
-            const int64_t rr = r + (n2_odd ? (r & 1) : 0);
+            const int64_t rr = (int64_t)r + (n2_odd ? (r & 1) : 0);
             if (r < 1 || (n2_odd && (r & 1)) || r > rows_cap || rr * per_row > lmax) {
                 snprintf(msg, sizeof msg, "tuning: rows_rpw %d does not fit the rows kernel (1..%lld%s)", r,
                          (long long)std::min<int64_t>(rows_cap, lmax / per_row), n2_odd ? ", even" : "");
