@@ -282,9 +282,11 @@ int fft3d_batch_submit_ex(const fft3d_batch_item* items, int n, int flags, hipSt
  * when no batched launch was staged, e.g. only radix-5/7 or odd-n2 items). */
 int fft3d_batch_submit_checked(const fft3d_batch_item* items, int n, hipStream_t stream, int64_t* token);
 /* Error bits of the batched launch(es) a token names, without waiting: 0
- * clean, else bit 1 (a dependency wait hit its spin limit: tiles skipped)
- * and/or bit 2 (a ticket queue had no workgroup on its XCD: its items did
- * not run) -- the results of such a launch are not valid.  FFT3D_ERR_BUSY
+ * clean, else bit 1 (a dependency wait hit its spin limit: tiles skipped),
+ * bit 2 (a ticket queue had no workgroup on its XCD: its items did not run)
+ * and/or bit 4 (a workgroup's ticket loop ran more iterations than its queue
+ * has tickets and was ended) -- the results of such a launch are not
+ * valid.  FFT3D_ERR_BUSY
  * while the launch has not finished; FFT3D_ERR_INVALID_ARG for an unknown
  * token or one older than the last 256 ring launches of its device. */
 int fft3d_batch_check(int64_t token);
@@ -303,8 +305,8 @@ int fft3d_batch_check(int64_t token);
  * (about 680 ROUNDTRIP items with split planes); a larger batch returns
  * FFT3D_ERR_UNSUPPORTED and enqueues nothing.  status: NULL, or a device int
  * that receives the launch's error bits (as fft3d_batch_check: 0 clean, bit 1
- * a wait hit its spin limit, bit 2 a queue had no workgroup) behind it on the
- * stream.  Every call on a device shares that device's array: calls on one
+ * a wait hit its spin limit, bit 2 a queue had no workgroup, bit 4 a ticket
+ * loop was ended by its iteration bound) behind it on the stream.  Every call on a device shares that device's array: calls on one
  * device must not overlap in time (issue them on one stream, or order them
  * with events); overlapping calls race and give wrong results. */
 int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status, hipStream_t stream);
@@ -327,7 +329,8 @@ int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
 /* Error bits of the last finished launch (synchronises the device):
  * 0 = clean, bit 1 = a dependency wait hit its spin limit (its tiles
  * skipped), bit 2 = a ticket queue had no workgroup on its XCD (its items
- * did not run). */
+ * did not run), bit 4 = a workgroup's ticket loop ran more iterations than
+ * its queue has tickets and was ended. */
 int fft3d_batch_status(fft3d_batch_t b);
 /* JSON: items, tickets, grid, LDS bytes, graph, and the tasks in ticket
  * order as [kind, dtype, tiles, index of the task waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */

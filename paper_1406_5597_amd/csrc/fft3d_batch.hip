@@ -144,13 +144,20 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(const void* __restrict__ ima
     auto first_of = [&](int i) { return cached ? s_firsts[i] : firsts[i]; };
     const int total = q >= 0 ? first_of(nq) : 0;
     // thread 0's scheduling state
-    int next = 0, cur = 0, checked = -1, failed = -1;
+    int next = 0, cur = 0, checked = -1, failed = -1, iters = 0;
     if (threadIdx.x == 0 && q >= 0) next = atomicAdd(ticket, 1);
     for (;;) {
         if (threadIdx.x == 0) {
             const int t = next;
             int k = -1, tile = 0, skip = 0;
-            if (t < total) {
+            // Every iteration but the last runs a distinct ticket of the
+            // queue, so a workgroup iterates at most total + 1 times.  The
+            // bound does not depend on memory: were the ticket state ever to
+            // stop advancing, the loop would still end (with an error bit)
+            // instead of running one ticket forever.
+            if (++iters > total + 1) {
+                atomicOr(&ctr[kBatchCtrErr], kBatchErrLoop);
+            } else if (t < total) {
                 next = atomicAdd(ticket, 1);  // the next ticket, while this one runs
                 // task of ticket t: firsts[cur] <= t (tickets only grow)
                 if (first_of(cur + 1) <= t) {

@@ -90,6 +90,8 @@ constexpr int kBatchCtrHeader = kBatchCtrErr + 16;
 // error bits
 constexpr int kBatchErrWait = 1;   // a dependency wait hit its spin limit
 constexpr int kBatchErrQueue = 2;  // a queue's XCD had no workgroup: its items did not run
+constexpr int kBatchErrLoop = 4;   // a workgroup's ticket loop ran more iterations than its queue has
+                                   // tickets (its ticket state stopped advancing) and was ended
 
 // Polls of a dependency wait before it gives up (error bit kBatchErrWait).
 constexpr int kBatchSpinLimit = 1 << 20;

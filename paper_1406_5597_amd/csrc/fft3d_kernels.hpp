@@ -613,6 +613,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const cx<T>* post = tw + a.off_post;
     const cx<T>* tw1 = tw + a.off_tw1;
     const int h = a.h, H = a.H, n1 = a.n1;
+    // a workgroup runs each ticket of its queue at most once: more iterations
+    // than the queue's tickets end the loop (error bit 8), whatever memory holds
+    const int max_iters = a.nslots * TT + 1;
+    int iters = 0;
     for (;;) {
         __syncthreads();  // the previous task is done with LDS and s_task
         if (threadIdx.x == 0) {
@@ -620,7 +624,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const int t = atomicAdd(ticket, 1);
             const int s = t / TT;
             k = t - s * TT;
-            if (s >= a.nslots) {
+            if (++iters > max_iters) {
+                atomicOr(&a.ctr[1], 8);
+            } else if (s >= a.nslots) {
                 atomicOr(&a.ctr[1], 4);
             } else if (k < first) {
                 // first phase of plane P(s)

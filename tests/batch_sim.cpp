@@ -19,6 +19,16 @@
 //     once, after all tiles of its dependency, and, when items are pinned,
 //     with every pass of an item on the item's XCD.
 // Prints "ok <tasks> <tickets> <lds> <pinned>" or "FAIL: why" (exit 1).
+//
+// "state lost" models thread 0's next-ticket word kept where it does not
+// hold its value -- an LDS address past the launch's LDS allocation, which
+// reads as zero and drops writes on this hardware -- and "bound 0" drops the
+// kernel's iteration bound (a workgroup runs at most its queue's tickets + 1
+// iterations).  With the state lost, the loop keeps running ticket 0: with
+// the bound every workgroup still leaves and the loop error bit is set
+// ("bounded <iterations>", exit 0); without it the simulation stops each
+// workgroup after 1000 times its queue's tickets and reports "unbounded"
+// (exit 3) -- the way such a launch never ends on the device.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -106,6 +116,7 @@ int main(int argc, char** argv)
     std::vector<int> dirs, works;
     BatchOptions o;
     int xcds = 8;
+    bool state_lost = false, bounded = true;
     char line[256];
     while (fgets(line, sizeof line, stdin)) {
         long long n0, n1, n2;
@@ -121,6 +132,14 @@ int main(int argc, char** argv)
         }
         if (sscanf(line, "xcds %d", &lag) == 1) {
             xcds = lag;
+            continue;
+        }
+        if (!strncmp(line, "state lost", 10)) {
+            state_lost = true;
+            continue;
+        }
+        if (sscanf(line, "bound %d", &lag) == 1) {
+            bounded = lag != 0;
             continue;
         }
         if (sscanf(line, "%lld %lld %lld %d %d %d", &n0, &n1, &n2, &dt, &dir, &work) != 6) continue;
@@ -271,7 +290,8 @@ int main(int argc, char** argv)
 
     // 3. the ticket protocol on G threads
     std::vector<std::atomic<int>> ticket((size_t)nq);
-    std::atomic<int> exited{0}, err{0};
+    std::atomic<int> exited{0}, err{0}, loop_err{0}, unbounded{0};
+    std::atomic<long long> iterations{0};
     std::vector<std::atomic<int>> done((size_t)nt);
     std::vector<std::vector<std::atomic<int>>> runs((size_t)nq);
     for (auto& t : ticket) t.store(0);
@@ -292,11 +312,31 @@ int main(int argc, char** argv)
         const int tb = tab.task_begin[(size_t)q], nqk = tab.task_begin[(size_t)q + 1] - tb;
         const int32_t* firsts = tab.firsts.data() + tb + q;
         const int total = firsts[nqk];
-        int nxt = ticket[(size_t)q].fetch_add(1), cur = 0, checked = -1;
+        // thread 0's next-ticket word: kept (registers), or lost (reads 0,
+        // writes dropped)
+        struct Word {
+            bool lost;
+            int v;
+            int get() const { return lost ? 0 : v; }
+            void set(int x) { if (!lost) v = x; }
+        } nxt{state_lost, 0};
+        nxt.set(ticket[(size_t)q].fetch_add(1));
+        int cur = 0, checked = -1;
+        long long iters = 0;
         for (;;) {
-            const int t = nxt;
+            ++iters;
+            if (bounded && iters > (long long)total + 1) {
+                loop_err.fetch_add(1);  // the kernel's bound: error bit, leave
+                break;
+            }
+            if (!bounded && iters > 1000LL * (total + 1)) {
+                unbounded.fetch_add(1);
+                break;
+            }
+            const int t = nxt.get();
             if (t >= total) break;
-            nxt = ticket[(size_t)q].fetch_add(1);
+            nxt.set(ticket[(size_t)q].fetch_add(1));
+            if (state_lost) cur = 0;  // the search state is lost the same way
             if (firsts[cur + 1] <= t) {
                 int lo = cur + 1, step = 1;
                 while (lo + step < nqk && firsts[lo + step] <= t) {
@@ -340,11 +380,23 @@ int main(int argc, char** argv)
             runs[(size_t)q][(size_t)t].fetch_add(1);
             done[(size_t)k].fetch_add(1);
         }
+        iterations.fetch_add(iters);
         exited.fetch_add(1);
     };
     std::vector<std::thread> th;
     for (int g = 0; g < G; ++g) th.emplace_back(wg, g);
     for (auto& x : th) x.join();
+    if (state_lost) {
+        if (exited.load() != G) return fail("a workgroup did not leave");
+        if (unbounded.load()) {
+            printf("unbounded %d\n", unbounded.load());
+            return 3;
+        }
+        if (loop_err.load() != G) return fail("lost state without the loop error bit");
+        printf("bounded %lld\n", iterations.load());
+        return 0;
+    }
+    if (loop_err.load() || unbounded.load()) return fail("the iteration bound ended a correct launch");
     if (err.load()) return fail("protocol error " + std::to_string(err.load()));
     if (exited.load() != G) return fail("a workgroup did not leave");
     for (int q = 0; q < nq; ++q)

@@ -117,3 +117,21 @@ def test_pinning_choice(sim):
     assert sim(even, workgroups=64)[3]
     assert sim(even, workgroups=12, xcds=4, mode=1)[3]
     assert not sim(even, workgroups=12, xcds=1)[3]
+
+
+def test_lost_ticket_state_ends_by_the_iteration_bound(sim):
+    """Thread 0's next-ticket word kept where it does not hold its value (LDS
+    past the launch's allocation reads zero and drops writes): the ticket loop
+    runs ticket 0 again and again.  Without an iteration bound it never ends
+    (the simulation gives up and says "unbounded"); with the kernel's bound
+    (at most the queue's tickets + 1 iterations) every workgroup leaves and
+    the loop error bit is set."""
+    items = [item((64, 64, 64), "f32", 2), item((32, 32, 32), "f64", 2)]
+    for mode in ("", "mode 2\n"):
+        head = mode + "state lost\n"
+        p = subprocess.run([sim.exe, "16"], input=head + "\n".join(items) + "\n", capture_output=True, text=True,
+                           timeout=120)
+        assert p.returncode == 0 and p.stdout.startswith("bounded"), p.stdout + p.stderr
+        p = subprocess.run([sim.exe, "16"], input=head + "bound 0\n" + "\n".join(items) + "\n",
+                           capture_output=True, text=True, timeout=120)
+        assert p.returncode == 3 and p.stdout.startswith("unbounded"), p.stdout + p.stderr
