@@ -414,6 +414,29 @@ template <int SP, typename T> __device__ __forceinline__ void store_cx(cx<T>* p,
     }
 }
 
+// Lane-pair exchange (lanes 2i and 2i+1 swap a value; DPP quad_perm
+// [1,0,3,2], no LDS).  Global IO of FP32 complex values uses it to move two
+// neighbouring values (16 bytes) per lane and access: each lane of a pair
+// loads or stores both values of one of two positions, and the pair swaps
+// one value each, so that every lane still ends with its own values.
+__device__ __forceinline__ float swap_pair_lane(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double swap_pair_lane(double x) { return x; }  // never called: FP32 only
+template <typename T> __device__ __forceinline__ cx<T> swap_pair_lane_cx(cx<T> v)
+{
+    return mk<T>(swap_pair_lane(v.x), swap_pair_lane(v.y));
+}
+
+// Whether a global IO accessor offers the paired 16-byte accesses.
+template <class O, class = void> struct io_pairs {
+    static constexpr bool value = false;
+};
+template <class O> struct io_pairs<O, decltype((void)O::kPair, void())> {
+    static constexpr bool value = O::kPair;
+};
+
 // W consecutive columns of a row-major block: line w = column w (only the
 // first `width` exist; the others read as zero and are not written),
 // element i = row i at stride S.  src and dst may be equal.  LP / SP: cache
@@ -453,6 +476,27 @@ template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct ColTileIO {
     }
     __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
     __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+    // Paired access: columns w (even) and w + 1 of a row as one 16-byte
+    // access (needs an even number of existing columns, so that a pair is
+    // whole or absent, an even row stride and 16-byte aligned tile
+    // pointers).  Off: a paired access then touches two rows nb apart (eight
+    // row segments per wave instead of four), and the FP32 n0 passes at
+    // 512^3 ran 16-25% slower with it (218 -> 275 us forward).
+    static constexpr bool kPair = false;
+    __device__ __forceinline__ bool pair_ld_ok() const
+    {
+        return (width & 1) == 0 && (S & 1) == 0 && ((uintptr_t)src & 15) == 0;
+    }
+    __device__ __forceinline__ bool pair_st_ok() const
+    {
+        return (width & 1) == 0 && (S & 1) == 0 && ((uintptr_t)dst & 15) == 0;
+    }
+    __device__ __forceinline__ bool pair_valid(Pos p) const { return p.ok; }
+    __device__ __forceinline__ float4 get2(Pos p) const { return *reinterpret_cast<const float4*>(src + p.off); }
+    __device__ __forceinline__ void put2(Pos p, cx<T> lo, cx<T> hi) const
+    {
+        *reinterpret_cast<float4*>(dst + p.off) = make_float4(lo.x, lo.y, hi.x, hi.y);
+    }
 };
 
 // Contiguous lines of `len` elements: line q, element i at q*len + i.
@@ -469,6 +513,18 @@ template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct RowsIO {
     __device__ __forceinline__ void put(Pos p, cx<T> v) const { store_cx<SP, T>(dst + p, v); }
     __device__ __forceinline__ cx<T> ld(int w, int i) const { return get(at(w, i)); }
     __device__ __forceinline__ void st(int w, int i, cx<T> v) const { put(at(w, i), v); }
+    // Paired access (FP32, plain policies): elements i (even) and i + 1 of a
+    // line as one 16-byte access; needs an even line length and 16-byte
+    // aligned pointers.
+    static constexpr bool kPair = sizeof(T) == 4 && LP == LD_PLAIN && SP == ST_PLAIN;
+    __device__ __forceinline__ bool pair_ld_ok() const { return (len & 1) == 0 && ((uintptr_t)src & 15) == 0; }
+    __device__ __forceinline__ bool pair_st_ok() const { return (len & 1) == 0 && ((uintptr_t)dst & 15) == 0; }
+    __device__ __forceinline__ bool pair_valid(Pos) const { return true; }
+    __device__ __forceinline__ float4 get2(Pos p) const { return *reinterpret_cast<const float4*>(src + p); }
+    __device__ __forceinline__ void put2(Pos p, cx<T> lo, cx<T> hi) const
+    {
+        *reinterpret_cast<float4*>(dst + p) = make_float4(lo.x, lo.y, hi.x, hi.y);
+    }
 };
 
 // Whole n1 x H planes, contiguous: line w = column (w mod H) of plane
@@ -521,6 +577,18 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
     const int nb = a.n / R;         // butterflies per line
     const int B = nb * a.nlines;    // butterflies in the tile
     const int Ns = a.Ns;
+    // Paired 16-byte global accesses (see swap_pair_lane): lanes 2i, 2i+1
+    // hold neighbouring lines (LINES_FAST) or neighbouring butterflies of a
+    // line, whose values are neighbours in memory -- on input always, on
+    // output when the stage's Ns is even (rows) -- given an even count of
+    // lines (butterflies per line).  Both lanes of a pair are active or
+    // neither (B is even then).  The arithmetic is unchanged.
+    constexpr bool kPairIn = io_pairs<In>::value && R % 2 == 0;
+    constexpr bool kPairOut = io_pairs<Out>::value && R % 2 == 0;
+    const bool even_pairs = LINES_FAST ? (a.nlines & 1) == 0 : (nb & 1) == 0;
+    bool pair_in = false, pair_out = false;
+    if constexpr (kPairIn) pair_in = even_pairs && in.pair_ld_ok();
+    if constexpr (kPairOut) pair_out = even_pairs && (LINES_FAST || (Ns & 1) == 0) && out.pair_st_ok();
     cx<T> v[KMAX][R];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
@@ -529,9 +597,29 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
             int j, w;
             butterfly_of<R, LINES_FAST>(b, a, j, w);
             if constexpr (In::kLinear) {
-                const auto p0 = in.at(w, j);
+                bool done = false;
+                if constexpr (kPairIn) {
+                    if (pair_in) {
+                        const int odd = b & 1;
+                        const auto p0 = LINES_FAST ? in.at(w - odd, j) : in.at(w, j - odd);
+                        const bool ok = in.pair_valid(p0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[k][r] = in.get(in.adv(p0, r * nb));
+                        for (int r = 0; r < R; r += 2) {
+                            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                            if (ok) q = in.get2(in.adv(p0, (r + odd) * nb));
+                            const cx<T> lo = mk<T>(q.x, q.y), hi = mk<T>(q.z, q.w);
+                            const cx<T> recv = swap_pair_lane_cx<T>(odd ? lo : hi);
+                            v[k][r] = odd ? recv : lo;
+                            v[k][r + 1] = odd ? hi : recv;
+                        }
+                        done = true;
+                    }
+                }
+                if (!done) {
+                    const auto p0 = in.at(w, j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[k][r] = in.get(in.adv(p0, r * nb));
+                }
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[k][r] = in.ld(w, j + r * nb);
@@ -555,9 +643,27 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
             const int m = j - fdiv(j, a.mg_ns) * Ns;
             const int base = (j - m) * R + m;
             if constexpr (Out::kLinear) {
-                const auto q0 = out.at(w, base);
+                bool done = false;
+                if constexpr (kPairOut) {
+                    if (pair_out) {
+                        const int odd = b & 1;
+                        const auto q0 = LINES_FAST ? out.at(w - odd, base) : out.at(w, base - odd);
+                        const bool ok = out.pair_valid(q0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[k][r]);
+                        for (int r = 0; r < R; r += 2) {
+                            const cx<T> recv = swap_pair_lane_cx<T>(odd ? v[k][r] : v[k][r + 1]);
+                            const cx<T> lo = odd ? recv : v[k][r];
+                            const cx<T> hi = odd ? v[k][r + 1] : recv;
+                            if (ok) out.put2(out.adv(q0, (r + odd) * Ns), lo, hi);
+                        }
+                        done = true;
+                    }
+                }
+                if (!done) {
+                    const auto q0 = out.at(w, base);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[k][r]);
+                }
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) out.st(w, base + r * Ns, v[k][r]);
