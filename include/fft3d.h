@@ -347,12 +347,18 @@ int fft3d_batch_destroy(fft3d_batch_t b);
  *   widen: 1 small fields get fewer, larger tiles (several planes per plane
  *          tile, column tiles widened to the tier; the rule), 2 the plans'
  *          own tile shapes;
- *   wg_per_cu: workgroups per CU (rule: as many as fit). */
+ *   wg_per_cu: workgroups per CU (rule: as many as fit);
+ *   spin_limit: polls of a dependency wait before it gives up (error bit 1:
+ *               the waiting task's tiles are skipped, every later wait gives
+ *               up at once, the launch still ends); rule 2^20; negative: no
+ *               poll at all -- every dependent task fails at once, which
+ *               tests the error path without a slow or stuck launch. */
 typedef struct {
     int32_t mode;
     int32_t lag;
     int32_t widen;
     int32_t wg_per_cu;
+    int32_t spin_limit;
 } fft3d_batch_tuning;
 
 /* fft3d_batch_create with a launch shape (bt NULL: the rule).  Out-of-range

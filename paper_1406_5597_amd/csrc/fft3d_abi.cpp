@@ -302,6 +302,7 @@ fft3d::BatchOptions batch_options(int device, const fft3d_batch_tuning* bt = nul
         o.lag = bt->lag;
         o.widen = bt->widen != 2;
         o.wg_per_cu = bt->wg_per_cu;
+        o.spin_limit = bt->spin_limit == 0 ? fft3d::kBatchSpinLimit : std::max(0, bt->spin_limit);
     }
     return o;
 }
@@ -811,7 +812,7 @@ int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, co
     if (!(flags & FFT3D_BATCH_DIRECT)) {
         b->args.image = b->image;
         b->args.ctr = b->ctr;
-        b->args.spin = fft3d::kBatchSpinLimit;
+        b->args.spin = b->tab.spin_limit;
         void* params[] = {&b->args.image, &b->args.ctr, &b->args.spin};
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);

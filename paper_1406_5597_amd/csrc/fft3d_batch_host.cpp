@@ -315,6 +315,7 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
     tab.task_begin[(size_t)nq] = (int)tab.tasks.size();
     tab.lds = lds;
     tab.wg_per_cu = o.wg_per_cu;
+    tab.spin_limit = o.spin_limit;
     return nullptr;
 }
 
@@ -367,7 +368,7 @@ hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
 hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void* dev_image, int* dev_ctr,
                                hipStream_t s)
 {
-    return launch_batch(grid, tab.lds, dev_image, dev_ctr, kBatchSpinLimit, s);
+    return launch_batch(grid, tab.lds, dev_image, dev_ctr, tab.spin_limit, s);
 }
 
 // ---------------------------------------------------------------- ring --

@@ -33,6 +33,8 @@ struct BatchOptions {
     bool widen = true;
     // workgroups per CU of the launch; 0: as many as fit
     int wg_per_cu = 0;
+    // polls of a dependency wait before it gives up (0: give up at once)
+    int spin_limit = kBatchSpinLimit;
 };
 
 struct BatchTable {
@@ -48,6 +50,7 @@ struct BatchTable {
     int64_t tickets = 0;
     size_t lds = 0;  // dynamic LDS of the launch (largest tile)
     int wg_per_cu = 0;  // workgroups per CU (0: as many as fit)
+    int spin_limit = kBatchSpinLimit;  // polls of a dependency wait
 };
 
 // LDS of one batch tile: half a CU's LDS less the kernel's own (scheduling

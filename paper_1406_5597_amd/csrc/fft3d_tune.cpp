@@ -869,7 +869,8 @@ int fft3d_batch_autotune(const fft3d_batch_item* items, int n, int effort, fft3d
     char b[256];
     snprintf(b, sizeof b,
              "{\"items\": %d, \"effort\": %d, \"ms_rule\": %s, \"ms_tuned\": %s, \"best\": {\"mode\": %d, \"lag\": %d, "
-             "\"widen\": %d, \"wg_per_cu\": %d}, \"candidates\": [",
-             n, effort, fmt_ms(ms_rule).c_str(), fmt_ms(inc).c_str(), pick.mode, pick.lag, pick.widen, pick.wg_per_cu);
+             "\"widen\": %d, \"wg_per_cu\": %d, \"spin_limit\": %d}, \"candidates\": [",
+             n, effort, fmt_ms(ms_rule).c_str(), fmt_ms(inc).c_str(), pick.mode, pick.lag, pick.widen, pick.wg_per_cu,
+             pick.spin_limit);
     return copy_out(std::string(b) + log + "]}", report, len);
 }

@@ -104,10 +104,10 @@ class Tuning(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     """fft3d_batch_tuning: every field 0 keeps the rule."""
-    _fields_ = [(n, ctypes.c_int32) for n in ("mode", "lag", "widen", "wg_per_cu")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("mode", "lag", "widen", "wg_per_cu", "spin_limit")]
 
     def to_dict(self) -> dict:
-        return {k: int(getattr(self, k)) for k in ("mode", "lag", "widen", "wg_per_cu")}
+        return {k: int(getattr(self, k)) for k in ("mode", "lag", "widen", "wg_per_cu", "spin_limit")}
 
 
 class ServerConfig(ctypes.Structure):

@@ -29,6 +29,11 @@
 // ("bounded <iterations>", exit 0); without it the simulation stops each
 // workgroup after 1000 times its queue's tickets and reports "unbounded"
 // (exit 3) -- the way such a launch never ends on the device.
+//
+// "spin N" gives every dependency wait the kernel's bound of N polls (N = 0:
+// none): a wait that runs out sets the error bit, its task's tiles are
+// skipped, and every later wait gives up at once.  The run must still end
+// with every workgroup gone; it prints "errbit <skipped tiles>" (exit 0).
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -117,6 +122,7 @@ int main(int argc, char** argv)
     BatchOptions o;
     int xcds = 8;
     bool state_lost = false, bounded = true;
+    int spin = -1;  // polls of a dependency wait; -1: wait (up to 60 s)
     char line[256];
     while (fgets(line, sizeof line, stdin)) {
         long long n0, n1, n2;
@@ -140,6 +146,10 @@ int main(int argc, char** argv)
         }
         if (sscanf(line, "bound %d", &lag) == 1) {
             bounded = lag != 0;
+            continue;
+        }
+        if (sscanf(line, "spin %d", &lag) == 1) {
+            spin = lag;
             continue;
         }
         if (sscanf(line, "%lld %lld %lld %d %d %d", &n0, &n1, &n2, &dt, &dir, &work) != 6) continue;
@@ -290,7 +300,7 @@ int main(int argc, char** argv)
 
     // 3. the ticket protocol on G threads
     std::vector<std::atomic<int>> ticket((size_t)nq);
-    std::atomic<int> exited{0}, err{0}, loop_err{0}, unbounded{0};
+    std::atomic<int> exited{0}, err{0}, loop_err{0}, unbounded{0}, wait_err{0}, skipped{0};
     std::atomic<long long> iterations{0};
     std::vector<std::atomic<int>> done((size_t)nt);
     std::vector<std::vector<std::atomic<int>>> runs((size_t)nq);
@@ -321,7 +331,7 @@ int main(int argc, char** argv)
             void set(int x) { if (!lost) v = x; }
         } nxt{state_lost, 0};
         nxt.set(ticket[(size_t)q].fetch_add(1));
-        int cur = 0, checked = -1;
+        int cur = 0, checked = -1, failed = -1;
         long long iters = 0;
         for (;;) {
             ++iters;
@@ -359,7 +369,22 @@ int main(int argc, char** argv)
             const BatchTask& tk = tab.tasks[(size_t)k];
             if (k != checked) {
                 checked = k;
-                if (tk.dep >= 0) {
+                if (tk.dep >= 0 && spin >= 0) {
+                    // the kernel's bounded wait
+                    bool ok = false;
+                    for (int it = 0; it < spin; ++it) {
+                        if (done[(size_t)tk.dep].load() >= tk.dep_tiles) {
+                            ok = true;
+                            break;
+                        }
+                        if (wait_err.load()) break;
+                        std::this_thread::yield();
+                    }
+                    if (!ok) {
+                        wait_err.store(1);
+                        failed = k;
+                    }
+                } else if (tk.dep >= 0) {
                     while (done[(size_t)tk.dep].load() < tk.dep_tiles) {
                         if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) {
                             err.store(2);
@@ -369,6 +394,13 @@ int main(int argc, char** argv)
                         std::this_thread::yield();
                     }
                 }
+            }
+            if (failed == k) {
+                // the tile is skipped and still counts itself done
+                skipped.fetch_add(1);
+                done[(size_t)k].fetch_add(1);
+                runs[(size_t)q][(size_t)t].fetch_add(1);
+                continue;
             }
             if (tk.dep >= 0 && done[(size_t)tk.dep].load() != tk.dep_tiles) err.store(3);
             if (tab.pinned) {
@@ -397,6 +429,17 @@ int main(int argc, char** argv)
         return 0;
     }
     if (loop_err.load() || unbounded.load()) return fail("the iteration bound ended a correct launch");
+    if (spin >= 0) {
+        if (exited.load() != G) return fail("a workgroup did not leave");
+        if (err.load()) return fail("protocol error " + std::to_string(err.load()));
+        for (int q = 0; q < nq; ++q)
+            for (size_t t = 0; t < runs[(size_t)q].size(); ++t)
+                if (runs[(size_t)q][t].load() != 1) return fail("a ticket ran more or less than once");
+        if (wait_err.load()) {
+            printf("errbit %d\n", skipped.load());
+            return 0;
+        }
+    }
     if (err.load()) return fail("protocol error " + std::to_string(err.load()));
     if (exited.load() != G) return fail("a workgroup did not leave");
     for (int q = 0; q < nq; ++q)

@@ -135,3 +135,19 @@ def test_lost_ticket_state_ends_by_the_iteration_bound(sim):
         p = subprocess.run([sim.exe, "16"], input=head + "bound 0\n" + "\n".join(items) + "\n",
                            capture_output=True, text=True, timeout=120)
         assert p.returncode == 3 and p.stdout.startswith("unbounded"), p.stdout + p.stderr
+
+
+def test_spin_limit_error_path(sim):
+    """The kernel's bounded dependency wait with no poll at all (spin 0):
+    every dependent task gives up at once, its tiles are skipped, the error
+    bit is set and every workgroup still leaves, each ticket taken once."""
+    items = [item((64, 64, 64), "f32", 2), item((32, 32, 32), "f64", 2), item((96, 96, 96), "f32", 2)]
+    for head in ("spin 0\n", "spin 0\nmode 2\n"):
+        p = subprocess.run([sim.exe, "16"], input=head + "\n".join(items) + "\n", capture_output=True, text=True,
+                           timeout=120)
+        assert p.returncode == 0 and p.stdout.startswith("errbit"), p.stdout + p.stderr
+        assert int(p.stdout.split()[1]) > 0
+    # a generous limit on the same items: no error, the normal checks
+    p = subprocess.run([sim.exe, "16"], input="spin 1000000\n" + "\n".join(items) + "\n", capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 0 and p.stdout.startswith("ok"), p.stdout + p.stderr

@@ -222,6 +222,31 @@ def test_batch_tile_shapes_give_same_bits(F, widen, wg):
     assert b.status() == 0
 
 
+def test_wait_error_path_ends_the_launch(F):
+    """Dependency waits that give up at once (batch tuning spin_limit < 0, no
+    poll): every second pass of an item fails its wait, its tiles are
+    skipped, and the launch still ends with error bit 1 -- twice in a row on
+    the same handle (the last workgroup clears the counters either way).  A
+    handle with the rule then computes the same items correctly."""
+    mix = fields.batch_mix(8, seed=23)
+    say("batch: wait error path")
+    items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 8300 + i) for i, (s, d) in enumerate(mix)]
+    for flags in (0, F.FFT3D_BATCH_DIRECT):
+        b = F.Batch([it.tuple() for it in items], flags=flags, tuning={"spin_limit": -1})
+        for _ in range(2):
+            b.launch()
+            _sync()
+            assert b.status() & 1
+    for it in items:
+        it.reset()
+    ok = F.Batch([it.tuple() for it in items])
+    ok.launch()
+    _sync()
+    assert ok.status() == 0
+    for it in items:
+        it.check_bits()
+
+
 def test_sequential_flag_matches(F):
     mix = fields.batch_mix(6, seed=8)
     say("batch: sequential flag")
