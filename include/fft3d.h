@@ -151,7 +151,8 @@ int fft3d_plan_ex(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, fft3
  * the candidates on the current device and returns the fastest. */
 typedef struct {
     int32_t plane;       /* 0 rule; FFT3D_TUNE_FUSED, FFT3D_TUNE_SPLIT or FFT3D_TUNE_COOP */
-    int32_t rows_rpw;    /* rows per tile of the rows kernels (split / cooperative plane step) */
+    int32_t rows_rpw;    /* rows per tile of the forward rows kernel (split / cooperative plane
+                            step) and of the cooperative step's row tasks */
     int32_t n1_w;        /* columns per tile of the n1 pass (power of two, <= 64) */
     int32_t n0_w;        /* columns per tile of the n0 pass (power of two, <= 64) */
     int32_t n0_group;    /* n0-pass tiles sent together to one XCD (>= 1) */
@@ -164,6 +165,7 @@ typedef struct {
     int32_t radix[3][8]; /* radix schedule of axis 0 (n0), 1 (n1), 2 (the rows: length n2/2 for
                             even n2, n2 for odd n2), first stage first, 0-terminated; radices 2, 3,
                             4, 8, 16, 5, 7 with product the axis length; all zero: rule */
+    int32_t rows_rpw_inv; /* rows per tile of the inverse rows kernel (split plane step) */
 } fft3d_tuning;
 
 enum { FFT3D_TUNE_FUSED = 1, FFT3D_TUNE_SPLIT = 2, FFT3D_TUNE_COOP = 3 };
@@ -179,7 +181,7 @@ int fft3d_plan_tuned(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, c
 /* Time the candidate tunings of an n0 x n1 x n2 plan of the given dtype on
  * the current device and return the fastest in *best (fields the search
  * left at the rule are 0).  The search, pass by pass with the plan's own
- * kernels (fft3d_run_pass): rows per rows tile; n1 and n0 tile widths and
+ * kernels (fft3d_run_pass): rows per tile of each rows kernel; n1 and n0 tile widths and
  * the n0 XCD grouping; the radix schedule of every axis; the plane step
  * (split against cooperative over lags 1..32 and task sizes); the walk
  * order; then whole r2c+c2r pairs of the rule plan against the tuned one (the

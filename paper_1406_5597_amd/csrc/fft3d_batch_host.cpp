@@ -90,15 +90,20 @@ const char* item_tiling(const Plan& p, bool widen, ItemTiling& t)
         }
         return nullptr;
     }
+    // one rows tile for both directions: the inverse kernel's (its LDS
+    // budget has no cut for a fourth workgroup a CU, which the batched
+    // kernel's registers never allow)
     bool rows_big = false;
     if (p.fused_plane) {
-        if (const char* why = split_tiling(p, t.rpw, rows_big, t.rows_lds, t.pass1)) return why;
+        int rpw_fwd = 1;
+        size_t lds_fwd = 0;
+        if (const char* why = split_tiling(p, rpw_fwd, rows_big, lds_fwd, t.rpw, t.rows_lds, t.pass1)) return why;
     } else {
         // split plans (the cooperative plane step is the split step in one
         // launch; both give the same bits)
-        t.rpw = p.rpw;
+        t.rpw = p.rpw_inv;
         rows_big = p.rows_big;
-        t.rows_lds = p.rows_lds;
+        t.rows_lds = p.rows_lds_inv;
         t.pass1 = p.pass1;
     }
     if (rows_big) return "rows too long for a small-tier tile";

@@ -673,6 +673,13 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
     if (END) __syncthreads();
 }
 
+// Largest radix a kernel instantiation carries code for: the fine column
+// tier leaves radix 16 out (the plan gives it radix <= 8 schedules only).
+template <typename T, int NT, int EPT> constexpr int max_radix()
+{
+    return (sizeof(T) == 4 && NT == kNtFine && EPT == kEptFine) ? kFineMaxRadix : 16;
+}
+
 template <bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In, class Out>
 __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
                                           const In& in, const Out& out, const cx<T>* __restrict__ tw)
@@ -686,7 +693,9 @@ __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines,
     a.mg_ns = S.mg_ns[s];
     const cx<T>* t = tw + S.twoff[s];
     switch (S.radix[s]) {
-    case 16: stage<16, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
+    case 16:
+        if constexpr (max_radix<T, NT, EPT>() >= 16) stage<16, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t);
+        break;
     case 8: stage<8, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     case 4: stage<4, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     case 3: stage<3, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;

@@ -33,11 +33,31 @@ template <typename T> struct Tier;
 template <> struct Tier<float> {
     static constexpr int kEptSmall = 16;  // 8192 elements, 64 KB
     static constexpr int kEptBig = 40;    // 20480 elements, 160 KB
+    // Waves per SIMD the small-tier rows kernels of even n2 are compiled for
+    // (a register bound): the forward kernel eight (64 VGPRs, four 512-thread
+    // workgroups a CU), the inverse six (80 VGPRs, three).  Measured at 512^3:
+    // rows r2c 226 -> 215 us (16 rows a tile), rows c2r 252 -> 222 us (it had
+    // needed 81 VGPRs, two workgroups a CU).
+    static constexpr int kRowsWavesFwd = 8;
+    static constexpr int kRowsWavesInv = 6;
 };
 template <> struct Tier<double> {
     static constexpr int kEptSmall = 8;   // 4096 elements, 64 KB
     static constexpr int kEptBig = 20;    // 10240 elements, 160 KB
+    // no bound: six waves spill the forward kernel and were slower both ways
+    static constexpr int kRowsWavesFwd = 1;
+    static constexpr int kRowsWavesInv = 1;
 };
+// Waves-per-SIMD bound of a rows kernel: the small tier's, none for the big.
+template <typename T, int EPT, bool INV> constexpr int rows_waves()
+{
+    return EPT == Tier<T>::kEptSmall ? (INV ? Tier<T>::kRowsWavesInv : Tier<T>::kRowsWavesFwd) : 1;
+}
+// ... of a column kernel: eight for the fine tier, none otherwise.
+template <typename T, int NT, int EPT> constexpr int cols_waves()
+{
+    return (sizeof(T) == 4 && NT == kNtFine && EPT == kEptFine) ? 8 : 1;
+}
 
 // Strided line pass over an array viewed as nbatch blocks of n rows by ncols
 // columns: element (b, i, c) at b*bstride + i*S + c.  Tiles are W consecutive
@@ -52,6 +72,7 @@ struct ColPass {
     int64_t tiles_per_batch = 0;
     bool big = false;     // kernel tier: big, or
     bool wide = false;    // ... wide (column kernels only), else small
+    bool fine = false;    // small tile on the fine tier (FP32, radix <= 8)
     size_t lds = 0;       // dynamic LDS bytes
 };
 
@@ -81,9 +102,11 @@ struct Plan {
     int ppw = 1;               // planes per workgroup (fused)
     bool plane_big = false;
     size_t plane_lds = 0;
-    int rpw = 1;               // rows per workgroup (split)
+    int rpw = 1;               // rows per workgroup (split), forward rows kernel
     bool rows_big = false;
     size_t rows_lds = 0;
+    int rpw_inv = 1;           // ... and of the inverse rows kernel (its own LDS budget)
+    size_t rows_lds_inv = 0;
     ColPass pass1;             // n1 columns of each plane (split)
     ColPass pass0;             // n0 columns over C (the strided step)
     ColPass pass0t;            // n0 columns of the transposed layout [n1][n0][H] (transpose-based method)
@@ -128,7 +151,10 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
 // Tiling of the split plane step (rows kernel + n1 column pass) for the
 // plan's shape and dtype, also for plans that fuse the plane step.  Returns
 // nullptr, or why the shape does not fit.
-const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, ColPass& pass1);
+// rpw / rows_lds: the forward rows kernel's tile; rpw_inv / rows_lds_inv the
+// inverse kernel's (same tier).
+const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, int& rpw_inv,
+                         size_t& rows_lds_inv, ColPass& pass1);
 // Small-tier tiling of the column pass along axis 0 (n0, over all C columns)
 // or 1 (n1, per plane): the widest power-of-two W whose tile fits the small
 // tier.  False if not even one column does.

@@ -221,7 +221,7 @@ __device__ __forceinline__ void rows_c2r_tile(const cx<T>* Xi, cx<T>* yz, int ro
 // ---- standalone kernels ----
 
 template <typename T, int NT, int EPT, bool INV>
-__global__ __launch_bounds__(NT) void k_cols(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
+__global__ __launch_bounds__(NT, (cols_waves<T, NT, EPT>())) void k_cols(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
                                              const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
                                              int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
                                              int64_t ntiles, int64_t ngroups, int gsize, int reverse)
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_cols(const cx<T>* in, cx<T>* out, const 
 
 // Split-plane forward: rpw real rows of length n2 -> rpw rows of H bins.
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
+__global__ __launch_bounds__(NT, (rows_waves<T, EPT, false>())) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
                                                  int rpw, int Hs, int reverse, int rs)
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(NT) void k_rows_r2c(const T* x, cx<T>* X, const Axi
 
 // Split-plane inverse: rpw rows of H bins -> rpw real rows of length n2.
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_rows_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
+__global__ __launch_bounds__(NT, (rows_waves<T, EPT, true>())) void k_rows_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                  const cx<T>* __restrict__ tw,
                                                  const cx<T>* __restrict__ post, int64_t nrows,
                                                  int rpw, int Hs, int reverse, int rs)
@@ -795,6 +795,10 @@ template <typename T> hipError_t init_plain()
     FFT3D_ALLOW((k_cols<T, kNtBig, EB, true>));
     FFT3D_ALLOW((k_cols<T, kNtWide, ES, false>));
     FFT3D_ALLOW((k_cols<T, kNtWide, ES, true>));
+    if constexpr (sizeof(T) == 4) {
+        FFT3D_ALLOW((k_cols<T, kNtFine, kEptFine, false>));
+        FFT3D_ALLOW((k_cols<T, kNtFine, kEptFine, true>));
+    }
     FFT3D_ALLOW((k_rows_r2c<T, kNtSmall, ES>));
     FFT3D_ALLOW((k_rows_r2c<T, kNtBig, EB>));
     FFT3D_ALLOW((k_rows_c2r<T, kNtSmall, ES>));
@@ -897,27 +901,27 @@ hipError_t rows_c2r_t(const Plan& p, const void* X, void* y, int64_t nrows, int 
                       bool padded = false)
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
-    const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
+    const unsigned grid = (unsigned)((nrows + p.rpw_inv - 1) / p.rpw_inv);
     const cx<T>* Xi = static_cast<const cx<T>*>(X);
     T* yo = static_cast<T*>(y);
     if (p.n2 & 1) {
         const uint32_t mgH = div_magic((uint32_t)p.H);
         const int rs = (int)(padded ? 2 * p.H : p.n2);
         if (p.rows_big)
-            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
+            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds_inv, st, Xi, yo,
+                               dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw_inv, p.Hs, mgH, rev, rs);
         else
-            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw, p.Hs, mgH, rev, rs);
+            hipLaunchKernelGGL((k_rows_c2r_odd<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds_inv, st, Xi,
+                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), nrows, p.rpw_inv, p.Hs, mgH, rev, rs);
         return hipGetLastError();
     }
     if (p.rows_big)
-        hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+        hipLaunchKernelGGL((k_rows_c2r<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds_inv, st, Xi, yo,
+                           dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw_inv, p.Hs, rev,
                            (int)(padded ? p.H : p.h));
     else
-        hipLaunchKernelGGL((k_rows_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs, rev,
+        hipLaunchKernelGGL((k_rows_c2r<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds_inv, st, Xi,
+                           yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw_inv, p.Hs, rev,
                            (int)(padded ? p.H : p.h));
     return hipGetLastError();
 }
@@ -944,7 +948,14 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
         hipLaunchKernelGGL((k_cols<T, kNtWide, ES, INV>), dim3(grid), dim3(kNtWide), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
-    else
+    else if (cp.fine) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_cols<T, kNtFine, kEptFine, INV>), dim3(grid), dim3(kNtFine), cp.lds, st, ci, co,
+                               ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
+                               div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
+        else
+            return hipErrorInvalidConfiguration;  // the plan marks FP32 passes only
+    } else
         hipLaunchKernelGGL((k_cols<T, kNtSmall, ES, INV>), dim3(grid), dim3(kNtSmall), cp.lds, st, ci, co,
                            ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);

@@ -249,6 +249,15 @@ static bool width_colpass(ColPass& cp, int64_t n, int W, int cxs, int es, int eb
     return true;
 }
 
+// A small FP32 column tile goes to the fine tier when every stage of its
+// schedule has radix <= 8 (the tile is the same 8192 elements).
+static void mark_fine(ColPass& cp, const AxisSched& ax)
+{
+    bool ok = !cp.big && !cp.wide && ax.nst > 0;
+    for (int i = 0; i < ax.nst; ++i) ok = ok && ax.radix[i] <= kFineMaxRadix;
+    cp.fine = ok;
+}
+
 bool small_colpass(const Plan& p, int axis, ColPass& cp)
 {
     const int cxs = 2 * p.elem;
@@ -257,15 +266,19 @@ bool small_colpass(const Plan& p, int axis, ColPass& cp)
     return make_colpass(cp, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, es, false);
 }
 
-const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, ColPass& pass1)
+const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_lds, int& rpw_inv,
+                         size_t& rows_lds_inv, ColPass& pass1)
 {
     const int cxs = 2 * p.elem;
     const int es = kNtSmall * (p.dtype ? Tier<double>::kEptSmall : Tier<float>::kEptSmall);
     const int eb = kNtBig * (p.dtype ? Tier<double>::kEptBig : Tier<float>::kEptBig);
     // rows per tile: what the small tier holds, within an LDS budget that
-    // lets three FP32 workgroups (two FP64) share a CU -- measured at 512^3:
-    // FP32 rows kernels 4.35 -> 4.72 TB/s with 16 rows instead of 32
+    // lets as many workgroups share a CU as the kernel's registers allow:
+    // FP32 three (the forward kernel of even n2 four), FP64 two -- measured
+    // at 512^3: FP32 rows kernels 4.35 -> 4.72 TB/s with 16 rows instead of
+    // 32 (three a CU), the forward one 226 -> 215 us at four a CU
     const int64_t budget = p.dtype == FFT3D_F64 ? 60 * 1024 : 48 * 1024;
+    const int64_t budget_fwd = p.dtype == FFT3D_F32 && p.n2 % 2 == 0 ? 40 * 1024 : budget;
     if (p.n2 % 2 != 0) {
         // odd n2: pairs of rows per complex line of n2 elements, an even
         // number of rows per tile (the last tile pairs its odd row with a
@@ -281,19 +294,28 @@ const char* split_tiling(const Plan& p, int& rpw, bool& rows_big, size_t& rows_l
         if (pairs < 1) return "n2 too large for one pair of rows in LDS";
         rpw = (int)std::min<int64_t>(2 * pairs, p.n0 * p.n1);
         rows_lds = (size_t)((rpw + (rpw & 1)) * p.Hs * cxs);
+        rpw_inv = rpw;
+        rows_lds_inv = rows_lds;
         if (!make_colpass(pass1, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, eb))
             return "n1 too large for a column tile";
         return nullptr;
     }
-    int64_t r = std::min<int64_t>(es / p.h, budget / ((int64_t)p.Hs * cxs));
+    // both directions take the same tier: the budgets differ only below
+    // what one small-tier row needs (FP32 rows of up to 4096 bins take
+    // 34 KB padded)
+    const int64_t per_row = (int64_t)p.Hs * cxs;
+    int64_t r = std::min<int64_t>(es / p.h, budget_fwd / per_row);
+    int64_t ri = std::min<int64_t>(es / p.h, budget / per_row);
     rows_big = false;
-    if (r < 1) {
-        r = std::min<int64_t>(eb / p.h, kLdsMax / ((int64_t)p.Hs * cxs));
+    if (r < 1 || ri < 1) {
+        r = ri = std::min<int64_t>(eb / p.h, kLdsMax / per_row);
         rows_big = true;
     }
     if (r < 1) return "n2 too large for one row in LDS";
     rpw = (int)std::min<int64_t>(r, p.n0 * p.n1);
-    rows_lds = (size_t)(rpw * p.Hs * cxs);
+    rows_lds = (size_t)(rpw * per_row);
+    rpw_inv = (int)std::min<int64_t>(ri, p.n0 * p.n1);
+    rows_lds_inv = (size_t)(rpw_inv * per_row);
     if (!make_colpass(pass1, p.n1, p.H, p.H, p.n0, p.n1 * p.H, cxs, es, eb)) return "n1 too large for a column tile";
     return nullptr;
 }
@@ -411,34 +433,38 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
     if (fused) {
         p.fused_plane = true;
         p.ppw = 1;
-        if (tu.rows_rpw || tu.n1_w || tu.coop_lag || tu.coop_rpw || tu.coop_w) {
-            why = "tuning: rows_rpw, n1_w and coop_* apply to split or cooperative plane steps only";
+        if (tu.rows_rpw || tu.rows_rpw_inv || tu.n1_w || tu.coop_lag || tu.coop_rpw || tu.coop_w) {
+            why = "tuning: rows_rpw, rows_rpw_inv, n1_w and coop_* apply to split or cooperative plane steps only";
             return FFT3D_ERR_INVALID_ARG;
         }
     } else {
         p.fused_plane = false;
-        const char* err = split_tiling(p, p.rpw, p.rows_big, p.rows_lds, p.pass1);
+        const char* err = split_tiling(p, p.rpw, p.rows_big, p.rows_lds, p.rpw_inv, p.rows_lds_inv, p.pass1);
         if (err) {
             why = err;
             return FFT3D_ERR_UNSUPPORTED;
         }
-        if (tu.rows_rpw) {
-            // up to what the rows kernel's tier holds (the rule keeps an
-            // LDS budget below that, for occupancy)
-            const int r = tu.rows_rpw;
-            const int64_t per_row = (int64_t)p.Hs * cxs;
-            const int64_t emax = p.rows_big ? eb : es, lmax = p.rows_big ? kLdsMax : kLdsHalf;
-            const int64_t rows_cap = n2_odd ? std::min<int64_t>(emax / n2, (int64_t)kNtSmall * kPairItems / p.H) * 2
-                                            : emax / p.h;
+        // rows per tile, forward and inverse: up to what the rows kernel's
+        // tier holds (the rule keeps an LDS budget below that, for occupancy)
+        const int64_t per_row = (int64_t)p.Hs * cxs;
+        const int64_t emax = p.rows_big ? eb : es, lmax = p.rows_big ? kLdsMax : kLdsHalf;
+        const int64_t rows_cap = n2_odd ? std::min<int64_t>(emax / n2, (int64_t)kNtSmall * kPairItems / p.H) * 2
+                                        : emax / p.h;
+        for (int inv = 0; inv < 2; ++inv) {
+            const int r = inv ? tu.rows_rpw_inv : tu.rows_rpw;
+            if (!r) continue;
             const int64_t rr = (int64_t)r + (n2_odd ? (r & 1) : 0);
             if (r < 1 || (n2_odd && (r & 1)) || r > rows_cap || rr * per_row > lmax) {
-                snprintf(msg, sizeof msg, "tuning: rows_rpw %d does not fit the rows kernel (1..%lld%s)", r,
+                snprintf(msg, sizeof msg, "tuning: %s %d does not fit the rows kernel (1..%lld%s)",
+                         inv ? "rows_rpw_inv" : "rows_rpw", r,
                          (long long)std::min<int64_t>(rows_cap, lmax / per_row), n2_odd ? ", even" : "");
                 why = msg;
                 return FFT3D_ERR_INVALID_ARG;
             }
-            p.rpw = (int)std::min<int64_t>(r, n0 * n1);
-            p.rows_lds = (size_t)((p.rpw + (n2_odd ? (p.rpw & 1) : 0)) * per_row);
+            int& rp = inv ? p.rpw_inv : p.rpw;
+            size_t& rl = inv ? p.rows_lds_inv : p.rows_lds;
+            rp = (int)std::min<int64_t>(r, n0 * n1);
+            rl = (size_t)((rp + (n2_odd ? (rp & 1) : 0)) * per_row);
         }
         if (tu.n1_w) {
             if (!width_colpass(p.pass1, n1, tu.n1_w, cxs, es, eb)) {
@@ -526,6 +552,13 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
             return FFT3D_ERR_INVALID_ARG;
         }
     }
+    // FP32 small column tiles of radix <= 8 schedules run on the fine tier
+    // (measured at 512^3: n1 passes 238 -> 234 us, pairs 1.3% faster)
+    if (dtype == FFT3D_F32) {
+        mark_fine(p.pass0, p.ax0);
+        mark_fine(p.pass0t, p.ax0);
+        if (!p.fused_plane) mark_fine(p.pass1, p.ax1);
+    }
     return FFT3D_OK;
 }
 
@@ -545,7 +578,8 @@ static std::string pass_json(const ColPass& c)
              "{\"row_stride\": %lld, \"ncols\": %lld, \"nbatch\": %lld, \"batch_stride\": %lld, "
              "\"W\": %d, \"tier\": \"%s\", \"grid\": %lld, \"lds\": %zu}",
              (long long)c.S, (long long)c.ncols, (long long)c.nbatch, (long long)c.bstride, c.W,
-             c.big ? "big" : (c.wide ? "wide" : "small"), (long long)(c.nbatch * c.tiles_per_batch), c.lds);
+             c.big ? "big" : (c.wide ? "wide" : (c.fine ? "fine" : "small")), (long long)(c.nbatch * c.tiles_per_batch),
+             c.lds);
     return b;
 }
 
@@ -569,9 +603,10 @@ std::string Plan::describe() const
     } else {
         snprintf(b, sizeof b,
                  "\"plane\": {\"kind\": \"%s\", \"rows_per_wg\": %d, \"tier\": \"%s\", \"grid\": %lld, "
-                 "\"lds\": %zu, ",
+                 "\"lds\": %zu, \"rows_per_wg_inv\": %d, \"grid_inv\": %lld, \"lds_inv\": %zu, ",
                  coop ? "coop" : "split", rpw, rows_big ? "big" : "small",
-                 (long long)((n0 * n1 + rpw - 1) / rpw), rows_lds);
+                 (long long)((n0 * n1 + rpw - 1) / rpw), rows_lds, rpw_inv,
+                 (long long)((n0 * n1 + rpw_inv - 1) / rpw_inv), rows_lds_inv);
         r += b;
         if (coop) {
             snprintf(b, sizeof b,
@@ -597,10 +632,10 @@ std::string Plan::describe() const
     if (tuned) {
         char t[256];
         snprintf(t, sizeof t,
-                 "\"tuning\": {\"plane\": %d, \"rows_rpw\": %d, \"n1_w\": %d, \"n0_w\": %d, \"n0_group\": %d, "
-                 "\"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
-                 tuning.plane, tuning.rows_rpw, tuning.n1_w, tuning.n0_w, tuning.n0_group, tuning.walk,
-                 tuning.coop_lag, tuning.coop_rpw, tuning.coop_w);
+                 "\"tuning\": {\"plane\": %d, \"rows_rpw\": %d, \"rows_rpw_inv\": %d, \"n1_w\": %d, \"n0_w\": %d, "
+                 "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
+                 tuning.plane, tuning.rows_rpw, tuning.rows_rpw_inv, tuning.n1_w, tuning.n0_w, tuning.n0_group,
+                 tuning.walk, tuning.coop_lag, tuning.coop_rpw, tuning.coop_w);
         r += t;
         for (int a = 0; a < 3; ++a) {
             r += a ? ", [" : "[";

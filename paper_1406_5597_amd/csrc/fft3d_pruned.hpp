@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_cols_pr(const cx<T>* in, cx<T>* out, con
 
 // Rows pass, forward: as k_rows_r2c, writing bins 0 .. Hw-1 of each row only.
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_rows_r2c_pr(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
+__global__ __launch_bounds__(NT, (rows_waves<T, EPT, false>())) void k_rows_r2c_pr(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
                                                     const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
                                                     int64_t nrows, int rpw, int Hs, int Hw, uint32_t mgHw)
 {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NT) void k_rows_r2c_pr(const T* x, cx<T>* X, const 
 // Rows pass, inverse: as k_rows_c2r, reading bins 0 .. Hw-1 of each row only
 // (the others are zero).  mgHw = div_magic(Hw), mgZ = div_magic(H - Hw).
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_rows_c2r_pr(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
+__global__ __launch_bounds__(NT, (rows_waves<T, EPT, true>())) void k_rows_c2r_pr(const cx<T>* X, T* y, const AxisSched* __restrict__ axp,
                                                     const cx<T>* __restrict__ tw, const cx<T>* __restrict__ post,
                                                     int64_t nrows, int rpw, int Hs, int Hw, uint32_t mgHw,
                                                     uint32_t mgZ)
@@ -387,7 +387,8 @@ hipError_t rows_pr_t(const Plan& p, const void* in, void* out, bool inverse, con
 {
     constexpr int ES = Tier<T>::kEptSmall, EB = Tier<T>::kEptBig;
     const int64_t nrows = p.n0 * p.n1;
-    const unsigned grid = (unsigned)((nrows + p.rpw - 1) / p.rpw);
+    const int rpw = inverse ? p.rpw_inv : p.rpw;
+    const unsigned grid = (unsigned)((nrows + rpw - 1) / rpw);
     const int Hw = b.K2 + 1;
     if (!inverse) {
         const T* xi = static_cast<const T*>(in);
@@ -406,12 +407,12 @@ hipError_t rows_pr_t(const Plan& p, const void* in, void* out, bool inverse, con
         T* yo = static_cast<T*>(out);
         const uint32_t mg = div_magic((uint32_t)Hw), mgz = div_magic((uint32_t)(p.H - Hw));
         if (p.rows_big)
-            hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds, st, Xi, yo,
-                               dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw, p.Hs,
+            hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtBig, EB>), dim3(grid), dim3(kNtBig), p.rows_lds_inv, st, Xi, yo,
+                               dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw_inv, p.Hs,
                                Hw, mg, mgz);
         else
-            hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds, st, Xi,
-                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw,
+            hipLaunchKernelGGL((k_rows_c2r_pr<T, kNtSmall, ES>), dim3(grid), dim3(kNtSmall), p.rows_lds_inv, st, Xi,
+                               yo, dsched(p, 2), table<T>(p, p.off_ax2h), table<T>(p, p.off_post), nrows, p.rpw_inv,
                                p.Hs, Hw, mg, mgz);
     }
     return hipGetLastError();

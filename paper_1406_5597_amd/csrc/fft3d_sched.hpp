@@ -8,6 +8,14 @@ namespace fft3d {
 
 constexpr int kMaxStages = 12;
 
+// Fine tier of the FP32 column kernels: a small-tier tile (8192 elements) on
+// 1024 threads of 8 elements each, for schedules of radix <= 8 only.  Its
+// kernels carry no radix-16 code, which keeps them at eight waves per SIMD
+// (two 1024-thread workgroups on a CU).
+constexpr int kNtFine = 1024;
+constexpr int kEptFine = 8;
+constexpr int kFineMaxRadix = 8;
+
 // Division by an invariant d in [1, 2^16) of an index n with n*d < 2^32:
 // n / d = mulhi32(n, magic(d)) with magic(d) = floor(2^32/d) + 1, and
 // magic(1) = 0 meaning "n / 1 = n".  Exactness: n*magic/2^32 exceeds n/d by

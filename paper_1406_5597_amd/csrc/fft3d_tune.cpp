@@ -87,9 +87,10 @@ void put_tuning(std::string& o, const fft3d_tuning& t)
 {
     char b[256];
     snprintf(b, sizeof b,
-             "{\"plane\": %d, \"rows_rpw\": %d, \"n1_w\": %d, \"n0_w\": %d, \"n0_group\": %d, \"walk\": %d, "
-             "\"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
-             t.plane, t.rows_rpw, t.n1_w, t.n0_w, t.n0_group, t.walk, t.coop_lag, t.coop_rpw, t.coop_w);
+             "{\"plane\": %d, \"rows_rpw\": %d, \"rows_rpw_inv\": %d, \"n1_w\": %d, \"n0_w\": %d, "
+             "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
+             t.plane, t.rows_rpw, t.rows_rpw_inv, t.n1_w, t.n0_w, t.n0_group, t.walk, t.coop_lag, t.coop_rpw,
+             t.coop_w);
     o += b;
     for (int a = 0; a < 3; ++a) {
         o += a ? ", [" : "[";
@@ -263,7 +264,8 @@ bool read_tuning(const JVal& o, fft3d_tuning& t)
 {
     if (o.k != JVal::Obj) return false;
     t = fft3d_tuning{};
-    if (!int_field(o, "plane", t.plane) || !int_field(o, "rows_rpw", t.rows_rpw) || !int_field(o, "n1_w", t.n1_w) ||
+    if (!int_field(o, "plane", t.plane) || !int_field(o, "rows_rpw", t.rows_rpw) ||
+        !int_field(o, "rows_rpw_inv", t.rows_rpw_inv) || !int_field(o, "n1_w", t.n1_w) ||
         !int_field(o, "n0_w", t.n0_w) || !int_field(o, "n0_group", t.n0_group) || !int_field(o, "walk", t.walk) ||
         !int_field(o, "coop_lag", t.coop_lag) || !int_field(o, "coop_rpw", t.coop_rpw) ||
         !int_field(o, "coop_w", t.coop_w))
@@ -653,23 +655,29 @@ int fft3d_autotune(int64_t n0, int64_t n1, int64_t n2, int dtype, int effort, ff
         }
         if (!pick.empty()) set_radix(cur, ax, pick);
     }
-    // 2. rows per rows tile (split plane step)
+    // 2. rows per tile of the forward and of the inverse rows kernel (split
+    //    plane step), each timed on its own pass
     if (!rp.fused_plane) {
-        double inc = S.eval(cur, plane, "rows_rpw", "{\"rows_rpw\": \"rule\"}");
-        int pick = 0;
-        for (int r : {2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64}) {
-            if (r == rp.rpw) continue;
-            if (!effort && (r == 6 || r == 10 || r == 20 || r == 48)) continue;
-            fft3d_tuning t = cur;
-            t.rows_rpw = r;
-            snprintf(w, sizeof w, "{\"rows_rpw\": %d}", r);
-            const double ms = S.eval(t, plane, "rows_rpw", w);
-            if (better(ms, inc)) {
-                inc = ms;
-                pick = r;
+        for (int inv = 0; inv < 2; ++inv) {
+            const std::vector<int> ps = {inv ? FFT3D_PASS_PLANE_C2R : FFT3D_PASS_PLANE_R2C};
+            const char* field = inv ? "rows_rpw_inv" : "rows_rpw";
+            const int rule = inv ? rp.rpw_inv : rp.rpw;
+            double inc = S.eval(cur, ps, field, std::string("{\"") + field + "\": \"rule\"}");
+            int pick = 0;
+            for (int r : {2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 32, 48, 64}) {
+                if (r == rule) continue;
+                if (!effort && (r == 6 || r == 10 || r == 14 || r == 18 || r == 48)) continue;
+                fft3d_tuning t = cur;
+                (inv ? t.rows_rpw_inv : t.rows_rpw) = r;
+                snprintf(w, sizeof w, "{\"%s\": %d}", field, r);
+                const double ms = S.eval(t, ps, field, w);
+                if (better(ms, inc)) {
+                    inc = ms;
+                    pick = r;
+                }
             }
+            (inv ? cur.rows_rpw_inv : cur.rows_rpw) = pick;
         }
-        cur.rows_rpw = pick;
     }
     // 3. n1 tile width (split plane step)
     if (!n1p.empty()) {

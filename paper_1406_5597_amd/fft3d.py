@@ -75,12 +75,16 @@ class BatchItem(ctypes.Structure):
                 ("mid", ctypes.c_void_p), ("out", ctypes.c_void_p), ("work", ctypes.c_void_p)]
 
 
-TUNING_FIELDS = ("plane", "rows_rpw", "n1_w", "n0_w", "n0_group", "walk", "coop_lag", "coop_rpw", "coop_w")
+# the scalar fields of fft3d_tuning; the struct holds radix[3][8] between
+# coop_w and rows_rpw_inv
+TUNING_FIELDS = ("plane", "rows_rpw", "n1_w", "n0_w", "n0_group", "walk", "coop_lag", "coop_rpw", "coop_w",
+                 "rows_rpw_inv")
 
 
 class Tuning(ctypes.Structure):
     """fft3d_tuning: every field 0 keeps the plan's rule."""
-    _fields_ = [(n, ctypes.c_int32) for n in TUNING_FIELDS] + [("radix", (ctypes.c_int32 * 8) * 3)]
+    _fields_ = [(n, ctypes.c_int32) for n in TUNING_FIELDS[:9]] + [("radix", (ctypes.c_int32 * 8) * 3)] + \
+        [(n, ctypes.c_int32) for n in TUNING_FIELDS[9:]]
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tuning":

@@ -42,10 +42,11 @@ def same_bits(a, b):
 
 TILE_TUNINGS = {
     (64, 64, 64): [dict(plane=2), dict(plane=2, rows_rpw=4, n1_w=4), dict(n0_w=4, n0_group=1), dict(walk=64 + 63)],
-    (256, 256, 256): [dict(rows_rpw=4), dict(rows_rpw=32), dict(n1_w=4), dict(n1_w=32), dict(n0_w=8, n0_group=2),
+    (256, 256, 256): [dict(rows_rpw=4), dict(rows_rpw=32), dict(rows_rpw_inv=4), dict(rows_rpw=8, rows_rpw_inv=24),
+                      dict(n1_w=4), dict(n1_w=32), dict(n0_w=8, n0_group=2),
                       dict(n0_w=32, n0_group=1), dict(walk=64), dict(walk=64 + 63),
                       dict(plane=3), dict(plane=3, coop_lag=1), dict(plane=3, coop_lag=16, coop_rpw=4, coop_w=4)],
-    (96, 128, 384): [dict(rows_rpw=6), dict(plane=3, coop_lag=5), dict(n0_w=32, n0_group=3)],
+    (96, 128, 384): [dict(rows_rpw=6), dict(rows_rpw_inv=6), dict(plane=3, coop_lag=5), dict(n0_w=32, n0_group=3)],
 }
 
 

@@ -39,6 +39,37 @@ def test_tile_fields_take_effect(F):
         desc(F, (1024, 64, 64), n0_w=32)
 
 
+def test_rows_tiles_per_direction(F):
+    # FP32, even n2: the forward rows tile within 40 KB of LDS (four
+    # workgroups a CU), the inverse within 48 KB (three)
+    d = F.Plan(512, 512, 512, dtype="f32", host_only=True).describe()["plane"]
+    assert d["rows_per_wg"] == 16 and d["lds"] <= 40 * 1024 and d["grid"] == 512 * 512 // 16
+    assert d["rows_per_wg_inv"] == 20 and 40 * 1024 < d["lds_inv"] <= 48 * 1024
+    for shape, dtype in [((512, 512, 512), "f64"), ((16, 128, 243), "f32")]:
+        d = F.Plan(*shape, dtype=dtype, host_only=True).describe()["plane"]
+        assert d["rows_per_wg"] == d["rows_per_wg_inv"] and d["lds"] == d["lds_inv"]
+    d = desc(F, (512, 512, 512), rows_rpw_inv=8)
+    assert d["plane"]["rows_per_wg"] == 16 and d["plane"]["rows_per_wg_inv"] == 8
+    assert d["plane"]["grid_inv"] == 512 * 512 // 8 and d["tuning"]["rows_rpw_inv"] == 8
+    d = desc(F, (512, 512, 512), rows_rpw=12)
+    assert d["plane"]["rows_per_wg"] == 12 and d["plane"]["rows_per_wg_inv"] == 20
+
+
+def test_fine_column_tier(F):
+    # FP32 small column tiles of radix <= 8 schedules take the fine tier
+    d = F.Plan(512, 512, 512, dtype="f32", host_only=True).describe()
+    assert d["schedules"]["n0"]["radices"] == [8, 8, 8]
+    assert d["n0_pass"]["tier"] == "fine" and d["plane"]["n1_pass"]["tier"] == "fine"
+    assert d["n0_pass"]["lds"] == 512 * 16 * 8
+    d = F.Plan(512, 512, 512, dtype="f64", host_only=True).describe()
+    assert d["n0_pass"]["tier"] == "small" and d["plane"]["n1_pass"]["tier"] == "small"
+    d = desc(F, (512, 512, 512), radix=[[16, 16, 2], [], []])
+    assert d["n0_pass"]["tier"] == "small" and d["plane"]["n1_pass"]["tier"] == "fine"
+    d = F.Plan(256, 256, 256, dtype="f32", host_only=True).describe()
+    assert d["schedules"]["n0"]["radices"] == [16, 16] and d["n0_pass"]["tier"] == "small"
+    assert desc(F, (1024, 64, 64), n0_w=16)["n0_pass"]["tier"] == "wide"
+
+
 def test_plane_kinds(F):
     assert desc(F, (512, 512, 512), plane=F.FFT3D_TUNE_COOP, coop_lag=16, coop_rpw=10, coop_w=8)["plane"]["coop"] == {
         "row_tasks": 52, "col_tasks": 33, "rows_per_task": 10, "cols_per_task": 8, "lag": 16, "grid": 0,
@@ -62,7 +93,8 @@ def test_radix_schedules(F):
 
 @pytest.mark.parametrize("tuning,needle", [
     (dict(plane=1), "FUSED"), (dict(plane=4), "plane must be"), (dict(rows_rpw=100), "rows_rpw"),
-    (dict(rows_rpw=-1), "rows_rpw"), (dict(n1_w=3), "n1_w"), (dict(n1_w=128), "n1_w"), (dict(n0_w=12), "n0_w"),
+    (dict(rows_rpw=-1), "rows_rpw"), (dict(rows_rpw_inv=100), "rows_rpw_inv"), (dict(rows_rpw_inv=-3), "rows_rpw_inv"),
+    (dict(n1_w=3), "n1_w"), (dict(n1_w=128), "n1_w"), (dict(n0_w=12), "n0_w"),
     (dict(n0_group=-2), "n0_group"), (dict(walk=5), "walk"), (dict(walk=200), "walk"),
     (dict(coop_lag=4), "coop_"), (dict(plane=3, coop_lag=300), "coop_lag"), (dict(plane=3, coop_rpw=21), "coop_rpw"),
     (dict(plane=3, coop_w=3), "coop_w"), (dict(radix=[[16, 16, 4], [], []]), "radix[0]"),
@@ -77,6 +109,8 @@ def test_tunings_refused(F, tuning, needle):
 def test_fused_plans_refuse_split_fields(F):
     with pytest.raises(F.Fft3dError):
         F.Plan(64, 64, 64, dtype="f32", host_only=True, tuning=dict(rows_rpw=4))
+    with pytest.raises(F.Fft3dError):
+        F.Plan(64, 64, 64, dtype="f32", host_only=True, tuning=dict(rows_rpw_inv=4))
     with pytest.raises(F.Fft3dError):  # radix-5/7 or odd n2: no cooperative step
         F.Plan(40, 250, 256, dtype="f32", host_only=True, tuning=dict(plane=3))
 
