@@ -247,14 +247,17 @@ typedef struct {
     void* work;
 } fft3d_batch_item;
 
-/* Run every item in ONE persistent kernel launch on `stream` (the batched
- * form of the plane step and the strided n0 step, Sec. 2.1 items 1 and 3,
- * Sec. 2.2, over many fields at once).  Requires fft3d_init on the items'
- * device.  Each item becomes a chain of passes (the ones fft3d_r2c /
- * fft3d_c2r would launch); workgroups take tiles of all chains from ticket
- * counters (one per XCD when items are placed on XCDs, else one for all), a
- * pass waiting only for the previous pass of the same item.  Every result is
- * bit-identical to the item run alone.
+/* Run every item in a few batched launches on `stream` (the batched form of
+ * the plane step and the strided n0 step, Sec. 2.1 items 1 and 3, Sec. 2.2,
+ * over many fields at once).  Requires fft3d_init on the items' device.
+ * Each item becomes a chain of passes (the ones fft3d_r2c / fft3d_c2r would
+ * launch).  By rule (level mode, see fft3d_batch_tuning) the passes go into
+ * one launch per pass level, tile kind and dtype, each launch running that
+ * pass of many items at once, every pass in a later launch than the pass
+ * it reads.  The alternative is one persistent launch whose workgroups take
+ * tiles of all chains from ticket counters, a pass waiting for the previous
+ * pass of the same item.  Every result is bit-identical to the item run
+ * alone.
  * Items run CONCURRENTLY: a buffer one item writes (out, mid, work, and in
  * for C2R without work) must not overlap any buffer of another item; inputs
  * that are only read may be shared.  Plans must outlive the launch.
@@ -264,9 +267,9 @@ typedef struct {
  * pinned/device buffers fft3d_init set up (16 launches deep); a submit that
  * finds fewer free slots than it needs returns FFT3D_ERR_BUSY and enqueues
  * nothing.  Batches of more than 4096 passes are split into several
- * launches (one slot each).  The batched kernel's error bits (see
- * fft3d_batch_status) are kept per launch: fft3d_batch_submit_checked
- * returns a token to read them with.
+ * launches (one slot each).  The persistent kernel's error bits (see
+ * fft3d_batch_status; the level mode has none) are kept per launch:
+ * fft3d_batch_submit_checked returns a token to read them with.
  * Items whose extents have a factor 5 or 7, or an odd n2, run their own
  * kernels (as fft3d_r2c / fft3d_c2r), on the same stream after the batched
  * launch. */
@@ -295,28 +298,28 @@ int fft3d_batch_check(int64_t token);
 
 /* For callers that cannot allocate device or pinned memory (code under
  * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
- * fft3d_batch_submit with the task image and counter block of the batched
- * kernel in a static device array of the library (1 MiB per device, held
+ * fft3d_batch_submit (level mode) with the task image of the batched
+ * launches in a static device array of the library (1 MiB per device, held
  * until the process ends) instead of the ring.  Allocates nothing: copies the
  * task image (from a host buffer of the calling thread, pageable) into the
- * array, clears its counters with a fill kernel, launches, all on `stream`.
+ * array and enqueues the launches that read it, all on `stream`.
  * Requires fft3d_init on the items' device (which finds the array's address
  * there).  Items, validation (all or nothing), results (bit-identical to
  * fft3d_batch_submit's) and the handling of radix-5/7 or odd-n2 items as
- * fft3d_batch_submit.  Limit: one batched launch of at most 4096 passes
+ * fft3d_batch_submit.  Limit: one task image of at most 4096 passes
  * (about 680 ROUNDTRIP items with split planes); a larger batch returns
  * FFT3D_ERR_UNSUPPORTED and enqueues nothing.  status: NULL, or a device int
- * that receives the launch's error bits (as fft3d_batch_check: 0 clean, bit 1
- * a wait hit its spin limit, bit 2 a queue had no workgroup, bit 4 a ticket
- * loop was ended by its iteration bound) behind it on the stream.  Every call on a device shares that device's array: calls on one
+ * that receives the launch's error bits behind it on the stream (always 0:
+ * the level mode has no waits that could give up).  Every call on a device shares that device's array: calls on one
  * device must not overlap in time (issue them on one stream, or order them
  * with events); overlapping calls race and give wrong results. */
 int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status, hipStream_t stream);
 
 /* A batch built once and launched many times: the task list and its counters
  * live in device memory owned by the handle (allocated here, synchronously),
- * and the launch is a hipGraph of one kernel node (instantiated here) unless
- * FFT3D_BATCH_DIRECT.  The item pointers are fixed at creation.  The same
+ * and the launch is a hipGraph (instantiated here: in level mode one kernel
+ * node per launch, each after the launches it reads from; persistent: one
+ * node) unless FFT3D_BATCH_DIRECT (the launches in order on the stream).  The item pointers are fixed at creation.  The same
  * concurrency rules as fft3d_batch_submit apply; at most 4096 passes.
  * Items whose extents have a factor 5 or 7, or an odd n2, are refused here
  * (FFT3D_ERR_UNSUPPORTED): the batched kernel has only the radix-2/3 stages
@@ -334,15 +337,25 @@ int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
  * did not run), bit 4 = a workgroup's ticket loop ran more iterations than
  * its queue has tickets and was ended. */
 int fft3d_batch_status(fft3d_batch_t b);
-/* JSON: items, tickets, grid, LDS bytes, graph, and the tasks in ticket
- * order as [kind, dtype, tiles, index of the task waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
+/* JSON: items, tickets, grid, LDS bytes, graph, mode, the level mode's
+ * launches as [kind, dtype, tasks, tiles, LDS bytes], and the tasks in ticket
+ * (level mode: launch) order as [kind, dtype, tiles, index of the task
+ * waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
 int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len);
 int fft3d_batch_destroy(fft3d_batch_t b);
 
 /* Launch shape of the batched kernel (what fft3d_batch_autotune chooses;
  * a zero field keeps the rule):
- *   mode: 1 pin every item to one XCD (one ticket queue per XCD), 2 one
- *         queue for all workgroups; rule: pin when that balances the XCDs;
+ *   mode: 0 (rule) or 3 level mode: one launch per pass level, tile kind
+ *         and dtype, each launch's kernel holding only its tile kind, each
+ *         pass in a later launch than the pass it reads (a batch handle's
+ *         graph runs a launch after the launches it reads from only; on a
+ *         stream, launch order is the only dependency), so lag, wg_per_cu
+ *         and spin_limit do not apply and the status is always 0;
+ *         the one persistent launch (ticket queues, bounded dependency
+ *         waits) with 1 every item pinned to one XCD (one ticket queue per
+ *         XCD), 2 one queue for all workgroups, 4 pinned when that balances
+ *         the XCDs, else one queue;
  *   lag: slots between an item's consecutive passes in the ticket order
  *        (rule: the number of items, i.e. every item's first pass, then
  *        every item's second pass, ...);

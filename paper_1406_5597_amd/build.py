@@ -39,6 +39,7 @@ SOURCES = [
     ("fft3d_pruned_f32.hip", DEVICE_FLAGS),
     ("fft3d_pruned_f64.hip", DEVICE_FLAGS),
     ("fft3d_batch.hip", DEVICE_FLAGS),
+    ("fft3d_level.hip", DEVICE_FLAGS),
     ("fft3d_coop_f32.hip", DEVICE_FLAGS),
     ("fft3d_coop_f64.hip", DEVICE_FLAGS),
     ("fft3d_batch_host.cpp", HOST_FLAGS),

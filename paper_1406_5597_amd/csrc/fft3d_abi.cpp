@@ -31,6 +31,13 @@ struct fft3d_batch_s {
         int* ctr;
         int spin;
     } args{};
+    // level mode: the arguments of each launch's graph node
+    struct LevelArgs {
+        const void* tasks;
+        const void* firsts;
+        int ntasks;
+    };
+    std::vector<LevelArgs> level_args;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~fft3d_batch_s()
@@ -289,10 +296,8 @@ std::vector<fft3d::BatchSpec> batch_specs(const fft3d_batch_item* items, int n)
     return v;
 }
 
-// Batch options for a device: its XCDs, and tuning overrides of the ticket
-// order (FFT3D_BATCH_LAG: slots between an item's passes) and of the queue
-// mode (FFT3D_BATCH_MODE: "pinned" or "spread"; default: pinned when that
-// balances the XCDs).
+// Batch options for a device: its XCDs, and the batch tuning's launch shape
+// (mode, ticket order, tile widening, workgroups per CU, spin limit).
 fft3d::BatchOptions batch_options(int device, const fft3d_batch_tuning* bt = nullptr)
 {
     fft3d::BatchOptions o;
@@ -310,7 +315,7 @@ fft3d::BatchOptions batch_options(int device, const fft3d_batch_tuning* bt = nul
 int check_batch_tuning(const fft3d_batch_tuning* bt, const char* who)
 {
     if (!bt) return FFT3D_OK;
-    if (bt->mode < 0 || bt->mode > 2) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": mode must be 0, 1 or 2");
+    if (bt->mode < 0 || bt->mode > 4) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": mode must be 0..4");
     if (bt->lag < 0) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": lag must be >= 0");
     if (bt->widen < 0 || bt->widen > 2) return fail(FFT3D_ERR_INVALID_ARG, std::string(who) + ": widen must be 0, 1 or 2");
     if (bt->wg_per_cu < 0 || bt->wg_per_cu > 16)
@@ -720,16 +725,20 @@ int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status,
                                                    " passes, more than the static scratch holds (" +
                                                    std::to_string(fft3d::kStaticTasks) + ")");
         const size_t img = fft3d::batch_image_bytes(tab);
-        if (img > fft3d::kStaticCtrOffset)
+        if (img > fft3d::kStaticScratchBytes || !tab.levels)
             return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": task image larger than the static scratch");
-        unsigned grid = 0;
-        if ((e = fft3d::batch_grid(tab, device, &grid)) != hipSuccess) return hip_fail(e, who);
         // host staging: this thread's buffer (no device or pinned memory)
         thread_local std::vector<char> host;
         host.resize(img);
         fft3d::write_batch_image(tab, host.data());
-        e = fft3d::launch_static_batch(device, host.data(), img, fft3d::kBatchCtrHeader + nt, grid, tab.lds, status, s);
-        if (e != hipSuccess) return hip_fail(e, who);
+        // the image, the level mode's launches (the rule; no counters, no
+        // waits), and a clean status
+        const void* dev = nullptr;
+        static const int zero = 0;
+        if ((e = fft3d::stage_static_image(device, host.data(), img, &dev, s)) != hipSuccess ||
+            (e = fft3d::enqueue_batch_image(tab, 0, dev, nullptr, s)) != hipSuccess ||
+            (status && (e = hipMemcpyAsync(status, &zero, sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess))
+            return hip_fail(e, who);
     } else if (status) {
         // no batched launch: report a clean launch
         static const int zero = 0;
@@ -809,7 +818,42 @@ int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, co
     if ((e = hipMemcpy(b->image, host.data(), img, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(b->ctr, 0, ctr)) != hipSuccess)
         return hip_fail(e, who);
-    if (!(flags & FFT3D_BATCH_DIRECT)) {
+    if (!(flags & FFT3D_BATCH_DIRECT) && b->tab.levels) {
+        // one kernel node per launch, each after the one before
+        const size_t toff = fft3d::level_tasks_offset(b->tab);
+        const fft3d::BatchTask* tasks =
+            reinterpret_cast<const fft3d::BatchTask*>(static_cast<const char*>(b->image) + toff);
+        const int32_t* firsts = static_cast<const int32_t*>(b->image);
+        b->level_args.resize(b->tab.launches.size());
+        if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_fail(e, "fft3d_batch_create: graph");
+        // each launch after the launches it reads from only: independent
+        // chains (the two dtypes, fused and split items) are parallel branches
+        std::vector<hipGraphNode_t> nodes;
+        for (size_t i = 0; i < b->tab.launches.size(); ++i) {
+            const fft3d::BatchLaunch& L = b->tab.launches[i];
+            fft3d_batch_s::LevelArgs& a = b->level_args[i];
+            a.tasks = tasks + L.task_begin;
+            a.firsts = firsts + L.firsts_begin;
+            a.ntasks = L.ntasks;
+            void* params[] = {&a.tasks, &a.firsts, &a.ntasks};
+            hipKernelNodeParams kp;
+            memset(&kp, 0, sizeof kp);
+            kp.func = const_cast<void*>(fft3d::level_kernel(L.kind, L.f64));
+            kp.gridDim = dim3((unsigned)L.tiles);
+            kp.blockDim = dim3(fft3d::kNtSmall);
+            kp.sharedMemBytes = (unsigned)L.lds;
+            kp.kernelParams = params;
+            std::vector<hipGraphNode_t> deps;
+            for (int d : L.deps) deps.push_back(nodes[(size_t)d]);
+            hipGraphNode_t node;
+            if ((e = hipGraphAddKernelNode(&node, b->graph, deps.empty() ? nullptr : deps.data(), deps.size(), &kp)) !=
+                hipSuccess)
+                return hip_fail(e, "fft3d_batch_create: graph");
+            nodes.push_back(node);
+        }
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return hip_fail(e, "fft3d_batch_create: graph");
+    } else if (!(flags & FFT3D_BATCH_DIRECT)) {
         b->args.image = b->image;
         b->args.ctr = b->ctr;
         b->args.spin = b->tab.spin_limit;
@@ -861,9 +905,16 @@ int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len)
     std::string d = "{\"items\": " + std::to_string(b->nitems) + ", \"tickets\": " + std::to_string(b->tab.tickets) +
                     ", \"grid\": " + std::to_string(b->grid) + ", \"lds\": " + std::to_string(b->tab.lds) +
                     ", \"graph\": " + (b->exec ? "true" : "false") + ", \"mode\": \"" +
-                    (b->tab.pinned ? "pinned" : "spread") + "\", \"queue_tickets\": [";
+                    (b->tab.levels ? "levels" : b->tab.pinned ? "pinned" : "spread") + "\", \"queue_tickets\": [";
     for (int q = 0; q < b->tab.nqueues; ++q)
         d += (q ? ", " : "") + std::to_string(b->tab.queue_tickets[(size_t)q]);
+    d += "], \"launches\": [";
+    for (size_t i = 0; i < b->tab.launches.size(); ++i) {
+        const fft3d::BatchLaunch& L = b->tab.launches[i];
+        d += (i ? ", " : "");
+        d += "[\"" + std::string(kinds[L.kind]) + "\", \"" + (L.f64 ? "f64" : "f32") + "\", " + std::to_string(L.ntasks) +
+             ", " + std::to_string(L.tiles) + ", " + std::to_string(L.lds) + "]";
+    }
     d += "], \"tasks\": [";
     for (size_t i = 0; i < b->tab.tasks.size(); ++i) {
         const fft3d::BatchTask& t = b->tab.tasks[i];

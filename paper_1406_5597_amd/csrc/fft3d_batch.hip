@@ -26,68 +26,22 @@
 #include <mutex>
 
 #include "fft3d_batch.hpp"
+#include "fft3d_batch_tiles.hpp"
 #include "fft3d_kernels.hpp"
 
 namespace fft3d {
 
+// One tile of any kind (the persistent kernel's dispatch).
 template <typename T, int EPT>
 __device__ __forceinline__ void batch_tile(const BatchTask& k, int tile, unsigned char* smem)
 {
-    constexpr int NT = kNtSmall;
-    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    const cx<T>* t0 = static_cast<const cx<T>*>(k.t0);
-    const cx<T>* t1 = static_cast<const cx<T>*>(k.t1);
     switch (k.kind) {
-    case kBkPlaneR2C:
-    case kBkPlaneC2R: {
-        const AxisSched& axh = *k.s0;
-        const AxisSched& ax1 = *k.s1;
-        const int h = axh.n, H = h + 1, n1 = ax1.n;
-        const int64_t p0 = (int64_t)tile * k.a0;
-        const int64_t left = k.i0 - p0;
-        const int np = left < k.a0 ? (int)left : k.a0;
-        const uint32_t mg = np == k.a0 ? k.m0 : div_magic_dev(np * H);
-        const cx<T>* t2 = static_cast<const cx<T>*>(k.t2);
-        if (k.kind == kBkPlaneR2C)
-            plane_r2c_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + p0 * n1 * h,
-                                       static_cast<cx<T>*>(k.out) + p0 * n1 * H, np, axh, ax1, t0, t1, t2, k.a1, mg,
-                                       k.m1, buf);
-        else
-            plane_c2r_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + p0 * n1 * H,
-                                       static_cast<cx<T>*>(k.out) + p0 * n1 * h, np, axh, ax1, t0, t1, t2, k.a1, mg,
-                                       k.m1, buf);
-        break;
-    }
-    case kBkRowsR2C:
-    case kBkRowsC2R: {
-        const AxisSched& axh = *k.s0;
-        const int h = axh.n, H = h + 1;
-        const int64_t r0 = (int64_t)tile * k.a0;
-        const int64_t left = k.i0 - r0;
-        const int rows = left < k.a0 ? (int)left : k.a0;
-        if (k.kind == kBkRowsR2C)
-            rows_r2c_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + r0 * h, static_cast<cx<T>*>(k.out) + r0 * H,
-                                      rows, k.a1, axh, t0, t1, buf);
-        else
-            rows_c2r_tile<T, NT, EPT>(static_cast<const cx<T>*>(k.in) + r0 * H, static_cast<cx<T>*>(k.out) + r0 * h,
-                                      rows, k.a1, axh, t0, t1, buf);
-        break;
-    }
-    default: {  // column passes
-        const int W = k.a0;
-        const int b = tile / k.a1;
-        const int64_t c0 = (int64_t)(tile - b * k.a1) * W;
-        const int64_t rem = k.i1 - c0;
-        const int width = rem < (int64_t)W ? (int)rem : W;
-        const int64_t off = (int64_t)b * k.i2 + c0;
-        const cx<T>* src = static_cast<const cx<T>*>(k.in) + off;
-        cx<T>* dst = static_cast<cx<T>*>(k.out) + off;
-        if (k.kind == kBkColsFwd)
-            col_tile<T, NT, EPT, false>(src, dst, k.i0, width, W, k.m0, *k.s0, t0, buf);
-        else
-            col_tile<T, NT, EPT, true>(src, dst, k.i0, width, W, k.m0, *k.s0, t0, buf);
-        break;
-    }
+    case kBkPlaneR2C: batch_tile_kind<T, EPT, kBkPlaneR2C>(k, tile, smem); break;
+    case kBkPlaneC2R: batch_tile_kind<T, EPT, kBkPlaneC2R>(k, tile, smem); break;
+    case kBkRowsR2C: batch_tile_kind<T, EPT, kBkRowsR2C>(k, tile, smem); break;
+    case kBkRowsC2R: batch_tile_kind<T, EPT, kBkRowsC2R>(k, tile, smem); break;
+    case kBkColsFwd: batch_tile_kind<T, EPT, kBkColsFwd>(k, tile, smem); break;
+    default: batch_tile_kind<T, EPT, kBkColsInv>(k, tile, smem); break;
     }
 }
 
@@ -198,8 +152,8 @@ __global__ __launch_bounds__(kNtSmall) void k_batch(const void* __restrict__ ima
         const int tile = __builtin_amdgcn_readfirstlane(s_task[1]);
         const int skip = __builtin_amdgcn_readfirstlane(s_task[2]);
         if (k < 0) break;
-        const BatchTask& tk = tasks[k];
         if (!skip) {
+            const BatchTask tk = rebased(tasks[k], image);
             if (tk.f64) batch_tile<double, Tier<double>::kEptSmall>(tk, tile, smem_raw);
             else batch_tile<float, Tier<float>::kEptSmall>(tk, tile, smem_raw);
         }
@@ -264,8 +218,9 @@ hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, 
 // ---- the allocation-free batched launch ----
 //
 // Callers that cannot allocate (code under graph capture, serving loops that
-// forbid hipMalloc) run a batch through this array: one task image and one
-// counter block per device, held until the process ends.  Every launch on a
+// forbid hipMalloc) run a batch through this array: one task image per
+// device (the level mode's launches read their tasks from it), held until the
+// process ends.  Every launch on a
 // device shares the device's copy, which keeps the last launch's contents;
 // launches that overlap in time on one device (unordered streams) race.  Host
 // code never passes the array's name to a kernel or a copy (in host code it
@@ -304,23 +259,13 @@ void* static_scratch(int device)
     return g_static_ptr[device];
 }
 
-hipError_t launch_static_batch(int device, const void* host_image, size_t bytes, int ctr_ints, unsigned grid,
-                               size_t lds, int* status, hipStream_t s)
+hipError_t stage_static_image(int device, const void* host_image, size_t bytes, const void** dev, hipStream_t s)
 {
     unsigned char* base = static_cast<unsigned char*>(static_scratch(device));
     if (!base) return hipErrorNotInitialized;
-    if (bytes > kStaticCtrOffset || ctr_ints < kBatchCtrHeader ||
-        kStaticCtrOffset + (size_t)ctr_ints * sizeof(int) > kStaticScratchBytes)
-        return hipErrorInvalidValue;
-    int* ctr = reinterpret_cast<int*>(base + kStaticCtrOffset);
-    hipError_t e = hipMemcpyAsync(base, host_image, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    // the counters must start at zero: a fill kernel, not a memset node
-    hipLaunchKernelGGL(k_zero_ints<0>, dim3(8), dim3(256), 0, s, ctr, (int64_t)ctr_ints);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_batch(grid, lds, base, ctr, kBatchSpinLimit, s)) != hipSuccess) return e;
-    if (status) e = hipMemcpyAsync(status, ctr + kBatchCtrStatus, sizeof(int), hipMemcpyDeviceToDevice, s);
-    return e;
+    if (bytes > kStaticScratchBytes) return hipErrorInvalidValue;
+    *dev = base;
+    return hipMemcpyAsync(base, host_image, bytes, hipMemcpyHostToDevice, s);
 }
 
 hipError_t probe_xcc_ids(int blocks, int* ids)

@@ -97,12 +97,10 @@ constexpr int kBatchErrLoop = 4;   // a workgroup's ticket loop ran more iterati
 constexpr int kBatchSpinLimit = 1 << 20;
 
 // The allocation-free batched launch (fft3d_batch_submit_static) keeps one
-// task image and one counter block per device in a static device array of
-// kStaticScratchBytes: the image at offset 0 (at most kStaticTasks passes,
-// kBatchMaxQueues queues), the counter block at kStaticCtrOffset.
+// task image per device in a static device array of kStaticScratchBytes (at
+// most kStaticTasks passes).
 constexpr int kStaticTasks = 4096;
 constexpr size_t kStaticScratchBytes = (size_t)1 << 20;
-constexpr size_t kStaticCtrOffset = (size_t)768 << 10;
 
 }  // namespace fft3d
 
@@ -117,6 +115,13 @@ const void* batch_kernel();
 hipError_t batch_occupancy(size_t lds, int* per_cu);
 // image: BatchHeader, ticket tables, tasks (see write_batch_image)
 hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, int spin_limit, hipStream_t s);
+// The level mode (fft3d_level.hip): the kernel of one tile kind and dtype,
+// and one launch of it over `ntasks` tasks (device pointers: the tasks, and
+// the first tile of each) with one workgroup per tile (grid = total tiles).
+hipError_t init_level();
+const void* level_kernel(int kind, int f64);
+hipError_t launch_level(int kind, int f64, unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts,
+                        int ntasks, hipStream_t s);
 // Hardware XCC id of every workgroup of a `blocks`-block probe launch
 // (synchronous; `ids` gets `blocks` values).
 hipError_t probe_xcc_ids(int blocks, int* ids);
@@ -126,11 +131,8 @@ hipError_t probe_xcc_ids(int blocks, int* ids);
 // is then found by device ordinal (nullptr before setup).
 hipError_t static_scratch_setup(int device);
 void* static_scratch(int device);
-// Copy a task image (host, `bytes` <= kStaticCtrOffset) into the device's
-// scratch, clear the counter block (ctr_ints ints) with a fill kernel, launch
-// the batched kernel on it and, if status is not NULL, copy the launch's
-// error bits to that device int behind it.  All on stream s, no allocation.
-hipError_t launch_static_batch(int device, const void* host_image, size_t bytes, int ctr_ints, unsigned grid,
-                               size_t lds, int* status, hipStream_t s);
+// Copy a task image (host, `bytes` <= kStaticScratchBytes) into the
+// device's scratch on stream s; *dev receives its device address.
+hipError_t stage_static_image(int device, const void* host_image, size_t bytes, const void** dev, hipStream_t s);
 
 }  // namespace fft3d

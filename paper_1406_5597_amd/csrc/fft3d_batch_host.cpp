@@ -212,6 +212,86 @@ int64_t task_cost_ns(const BatchTask& t)
     return (int64_t)t.ntiles * tile;
 }
 
+// The level mode's launches: each item's passes in order, pass L in the
+// first launch of its kind and dtype after the launch of pass L-1, or in a
+// new launch right after that one.  Inserting a launch keeps the order of
+// those already placed, so every pass stays after its predecessor.  Items
+// with the longest chains go first (they set the skeleton the others fit
+// into); within a launch, tasks with more tiles first.
+const char* build_levels(const std::vector<std::vector<BatchTask>>& chains, const std::vector<int64_t>& load,
+                         BatchTable& tab)
+{
+    struct Group {
+        int kind, f64;
+        std::vector<const BatchTask*> tasks;
+        std::vector<const BatchTask*> preds;  // the pass before each task (or null)
+    };
+    std::vector<Group> g;
+    const int n = (int)chains.size();
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const size_t la = chains[(size_t)a].size(), lb = chains[(size_t)b].size();
+        return la != lb ? la > lb : load[(size_t)a] > load[(size_t)b];
+    });
+    for (int i : order) {
+        int prev = -1;
+        const BatchTask* pred = nullptr;
+        for (const BatchTask& t : chains[(size_t)i]) {
+            int j = prev + 1;
+            while (j < (int)g.size() && !(g[(size_t)j].kind == t.kind && g[(size_t)j].f64 == t.f64)) ++j;
+            if (j == (int)g.size()) {
+                j = prev + 1;
+                g.insert(g.begin() + j, Group{t.kind, t.f64, {}, {}});
+            }
+            g[(size_t)j].tasks.push_back(&t);
+            g[(size_t)j].preds.push_back(pred);
+            prev = j;
+            pred = &t;
+        }
+    }
+    // the launch of every pass, for the launches' dependencies
+    std::vector<std::pair<const BatchTask*, int>> where;
+    for (size_t j = 0; j < g.size(); ++j)
+        for (const BatchTask* t : g[j].tasks) where.push_back({t, (int)j});
+    std::sort(where.begin(), where.end());
+    auto launch_of = [&](const BatchTask* t) {
+        return std::lower_bound(where.begin(), where.end(), std::make_pair(t, -1))->second;
+    };
+    for (Group& gr : g) {
+        BatchLaunch L;
+        for (const BatchTask* pr : gr.preds)
+            if (pr) L.deps.push_back(launch_of(pr));
+        std::sort(L.deps.begin(), L.deps.end());
+        L.deps.erase(std::unique(L.deps.begin(), L.deps.end()), L.deps.end());
+        std::stable_sort(gr.tasks.begin(), gr.tasks.end(),
+                         [](const BatchTask* a, const BatchTask* b) { return a->ntiles > b->ntiles; });
+        L.kind = gr.kind;
+        L.f64 = gr.f64;
+        L.task_begin = (int)tab.tasks.size();
+        L.ntasks = (int)gr.tasks.size();
+        L.firsts_begin = (int)tab.firsts.size();
+        for (const BatchTask* t : gr.tasks) {
+            tab.firsts.push_back((int32_t)L.tiles);
+            L.tiles += t->ntiles;
+            if (L.tiles > 0x3fffffff) return "too many tiles in one launch";
+            L.lds = std::max(L.lds, (size_t)t->lds);
+            BatchTask c = *t;
+            c.dep = -1;
+            c.dep_tiles = 0;
+            tab.tasks.push_back(c);
+        }
+        tab.firsts.push_back((int32_t)L.tiles);
+        tab.tickets += L.tiles;
+        tab.lds = std::max(tab.lds, L.lds);
+        tab.launches.push_back(L);
+    }
+    tab.levels = true;
+    tab.nqueues = 0;
+    tab.task_begin.assign(1, 0);
+    return nullptr;
+}
+
 }  // namespace
 
 const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions& o, BatchTable& tab)
@@ -239,6 +319,12 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
             lds = std::max(lds, (size_t)t.lds);
             load[(size_t)i] += task_cost_ns(t);
         }
+    }
+
+    if (o.mode == 0 || o.mode == 3) {
+        tab.wg_per_cu = o.wg_per_cu;
+        tab.spin_limit = o.spin_limit;
+        return build_levels(chains, load, tab);
     }
 
     // queues: one per XCD, items placed largest first on the least loaded
@@ -334,14 +420,26 @@ size_t batch_image_bytes(int ntasks, int nqueues)
     return batch_tasks_offset(ntasks, nqueues) + (size_t)ntasks * sizeof(BatchTask);
 }
 
+// Level mode: the first-tile tables, then the tasks.
+size_t level_tasks_offset(const BatchTable& tab) { return (tab.firsts.size() * sizeof(int32_t) + 255) & ~(size_t)255; }
+
 size_t batch_image_bytes(const BatchTable& tab)
 {
+    if (tab.levels) return level_tasks_offset(tab) + tab.tasks.size() * sizeof(BatchTask);
     return batch_image_bytes((int)tab.tasks.size(), tab.nqueues);
 }
 
 void write_batch_image(const BatchTable& tab, void* dst)
 {
     const int nt = (int)tab.tasks.size();
+    if (tab.levels) {
+        char* d = static_cast<char*>(dst);
+        const size_t off = level_tasks_offset(tab);
+        memset(d, 0, off);
+        memcpy(d, tab.firsts.data(), tab.firsts.size() * sizeof(int32_t));
+        memcpy(d + off, tab.tasks.data(), (size_t)nt * sizeof(BatchTask));
+        return;
+    }
     BatchHeader h;
     memset(&h, 0, sizeof h);
     h.nqueues = tab.nqueues;
@@ -373,6 +471,17 @@ hipError_t batch_grid(const BatchTable& tab, int device, unsigned* grid)
 hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void* dev_image, int* dev_ctr,
                                hipStream_t s)
 {
+    if (tab.levels) {
+        const int32_t* firsts = static_cast<const int32_t*>(dev_image);
+        const BatchTask* tasks = reinterpret_cast<const BatchTask*>(static_cast<const char*>(dev_image) +
+                                                                    level_tasks_offset(tab));
+        for (const BatchLaunch& L : tab.launches) {
+            const hipError_t e = launch_level(L.kind, L.f64, (unsigned)L.tiles, L.lds, tasks + L.task_begin,
+                                              firsts + L.firsts_begin, L.ntasks, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     return launch_batch(grid, tab.lds, dev_image, dev_ctr, tab.spin_limit, s);
 }
 
@@ -521,7 +630,8 @@ hipError_t ring_submit(int device, const BatchTable* tabs, int ntabs, hipStream_
     }
     std::vector<unsigned> grids((size_t)ntabs);
     for (int t = 0; t < ntabs; ++t) {
-        if ((int)tabs[t].tasks.size() > kRingTasks) {
+        if ((int)tabs[t].tasks.size() > kRingTasks ||
+            batch_image_bytes(tabs[t]) > batch_image_bytes(kRingTasks, kBatchMaxQueues)) {
             *why = "too many tasks for one ring slot";
             return hipErrorInvalidValue;
         }
@@ -549,8 +659,10 @@ hipError_t ring_submit(int device, const BatchTable* tabs, int ntabs, hipStream_
         const size_t bytes = batch_image_bytes(tabs[t]);
         hipError_t e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = enqueue_batch_image(tabs[t], grids[(size_t)t], sl.dev, sl.ctr, s);
-        // the launch's error bits, back to the host behind it
-        if (e == hipSuccess)
+        // the launch's error bits, back to the host behind it (the level
+        // mode has no waits and no error bits)
+        *sl.hstat = 0;
+        if (e == hipSuccess && !tabs[t].levels)
             e = hipMemcpyAsync(sl.hstat, sl.ctr + kBatchCtrStatus, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipEventRecord(sl.done, s);
         if (e != hipSuccess) return e;

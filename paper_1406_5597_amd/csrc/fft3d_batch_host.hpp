@@ -22,8 +22,11 @@ struct BatchSpec {
 struct BatchOptions {
     // the device's hardware XCC ids (one queue per XCD when pinned)
     std::vector<int> xcc_ids;
-    // 0: pin items to XCDs when that balances them, else one queue;
-    // 1: always pin; 2: never pin
+    // 0 (the rule) and 3: level mode (one launch per pass level, tile kind
+    // and dtype; no queues); the one persistent launch with 1: items pinned
+    // to XCDs (a queue per XCD), 2: one queue, 4: pinned when that balances
+    // the XCDs, else one queue.  Measured on the 64-field mix: 1.58 ms in
+    // level mode (a graph), 2.5-2.6 ms persistent.
     int mode = 0;
     // slots between an item's consecutive passes in the ticket order; 0 means
     // the number of items (pass-major order)
@@ -37,7 +40,28 @@ struct BatchOptions {
     int spin_limit = kBatchSpinLimit;
 };
 
+// One launch of the level mode: tasks task_begin .. task_begin+ntasks-1 (one
+// kind and dtype, passes of different items), the first tile of each at
+// firsts[firsts_begin ..]; one workgroup per tile.
+struct BatchLaunch {
+    int kind = 0;
+    int f64 = 0;
+    int task_begin = 0;
+    int ntasks = 0;
+    int firsts_begin = 0;
+    int64_t tiles = 0;
+    size_t lds = 0;
+    // earlier launches holding the passes this launch's tasks read (a graph
+    // runs the launch after these only; a stream after every earlier one)
+    std::vector<int> deps;
+};
+
 struct BatchTable {
+    // level mode: `launches` in stream order, every pass in a later launch
+    // than the pass it reads (firsts: per launch, the first tile of each of
+    // its tasks); the queue fields below are unused
+    bool levels = false;
+    std::vector<BatchLaunch> launches;
     std::vector<BatchTask> tasks;  // queue by queue
     // per queue: the first ticket (within the queue) of each of its tasks,
     // then its total; queue q's entries start at task_begin[q] + q
@@ -62,10 +86,12 @@ constexpr int kRingTasks = 4096;  // tasks per ring slot
 // Task list of n items; nullptr or why it cannot be built.
 const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions& o, BatchTable& tab);
 // Device image of a task list: BatchHeader, the per-queue ticket tables, then
-// the tasks (256-byte aligned).
+// the tasks (256-byte aligned); level mode: the launches' first-tile tables,
+// then the tasks (256-byte aligned).
 size_t batch_image_bytes(int ntasks, int nqueues);
 size_t batch_image_bytes(const BatchTable& tab);
 size_t batch_tasks_offset(int ntasks, int nqueues);
+size_t level_tasks_offset(const BatchTable& tab);  // level mode: offset of the tasks
 void write_batch_image(const BatchTable& tab, void* dst);
 // Workgroups of the launch: every CU times the workgroups that fit on one,
 // at most one per ticket.

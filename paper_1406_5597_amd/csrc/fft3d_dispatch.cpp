@@ -48,6 +48,7 @@ hipError_t kernels_init()
     (void)init_pruned_f32_odd();
     (void)init_pruned_f64_odd();
     (void)init_batch();
+    (void)init_level();
     (void)hipGetLastError();
     return hipSuccess;
 }

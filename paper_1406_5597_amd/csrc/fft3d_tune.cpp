@@ -861,12 +861,13 @@ int fft3d_batch_autotune(const fft3d_batch_item* items, int n, int effort, fft3d
     std::vector<int> lags = {0};
     if (effort)
         for (int l : {1, 2, 4, 8, 16}) lags.push_back(l);
-    for (int mode = 0; mode <= 2; ++mode)
+    for (int mode : {0, 1, 2, 4})
         for (int widen = 1; widen <= 2; ++widen)
             for (int wg = 0; wg <= 2; ++wg)
                 for (int lag : lags) {
-                    fft3d_batch_tuning bt{mode, lag, widen, wg};
+                    fft3d_batch_tuning bt{mode, lag, widen, wg, 0};
                     if (mode == 0 && widen == 1 && wg == 0 && lag == 0) continue;
+                    if (mode == 0 && (wg != 0 || lag != 0)) continue;  // level mode: no queues, a workgroup per tile
                     const double ms = eval(bt);
                     if (ms > 0 && ms < 0.99 * inc) {
                         inc = ms;

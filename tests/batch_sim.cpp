@@ -3,7 +3,8 @@
 //
 // Reads items from stdin, one per line: "n0 n1 n2 dtype dir work" (dtype 0
 // FP32 / 1 FP64, dir 0 R2C / 1 C2R / 2 ROUNDTRIP, work 0/1), and optional
-// lines "lag L", "mode M" (0 auto, 1 pinned, 2 spread), "xcds X" (the device
+// lines "lag L", "mode M" (4 auto, the default here; 1 pinned, 2 spread; 0 and 3
+// levels), "xcds X" (the device
 // has XCC ids 0..X-1; default 8).  Builds host-only plans and the batch's
 // task list with the library's own host code (fake, disjoint device
 // addresses), then:
@@ -19,6 +20,11 @@
 //     once, after all tiles of its dependency, and, when items are pinned,
 //     with every pass of an item on the item's XCD.
 // Prints "ok <tasks> <tickets> <lds> <pinned>" or "FAIL: why" (exit 1).
+//
+// Level mode ("mode 3"): checks 1 and 2 only -- every launch of one tile kind
+// and dtype, every item's passes those of the persistent table in the same
+// order and each in a later launch than its predecessor -- and prints
+// "ok levels <tasks> <launches> <tiles> <lds>".
 //
 // "state lost" models thread 0's next-ticket word kept where it does not
 // hold its value -- an LDS address past the launch's LDS allocation, which
@@ -38,6 +44,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <chrono>
@@ -58,6 +65,10 @@ hipError_t batch_occupancy(size_t, int* per_cu)
     return hipSuccess;
 }
 hipError_t launch_batch(unsigned, size_t, const void*, int*, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_level(int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
 hipError_t probe_xcc_ids(int, int*) { return hipErrorNotSupported; }
 }  // namespace fft3d
 
@@ -120,6 +131,7 @@ int main(int argc, char** argv)
     std::vector<Plan> plans;
     std::vector<int> dirs, works;
     BatchOptions o;
+    o.mode = 4;  // the persistent launch (pinned when balanced) unless "mode M" says otherwise
     int xcds = 8;
     bool state_lost = false, bounded = true;
     int spin = -1;  // polls of a dependency wait; -1: wait (up to 60 s)
@@ -199,32 +211,106 @@ int main(int argc, char** argv)
     const int nt = (int)tab.tasks.size();
     const int nq = tab.nqueues;
 
-    // 1. the table
-    if ((int)tab.task_begin.size() != nq + 1 || tab.task_begin[0] != 0 || tab.task_begin[(size_t)nq] != nt)
-        return fail("queue task ranges");
-    if ((int)tab.firsts.size() != nt + nq) return fail("ticket table size");
-    std::vector<int> qof((size_t)nt, -1);
-    int64_t all = 0;
-    for (int q = 0; q < nq; ++q) {
-        const int b = tab.task_begin[(size_t)q], e = tab.task_begin[(size_t)q + 1];
-        const int32_t* f = tab.firsts.data() + b + q;
-        if (f[0] != 0) return fail("queue tickets do not start at 0");
-        for (int k = b; k < e; ++k) {
-            qof[(size_t)k] = q;
-            const BatchTask& t = tab.tasks[(size_t)k];
-            if (t.ntiles < 1) return fail("empty task");
-            if (f[k - b + 1] - f[k - b] != t.ntiles) return fail("ticket table does not count tiles");
-            if (t.dep >= 0 && (t.dep < b || t.dep >= k)) return fail("task waits for a later task or another queue");
-            if (t.dep >= 0 && t.dep_tiles != tab.tasks[(size_t)t.dep].ntiles) return fail("dep_tiles");
-            if ((size_t)t.lds > tab.lds || (int64_t)tab.lds > kBatchLdsCap) return fail("LDS over budget");
+    auto owner_of = [&](const void* p) -> int {
+        for (int i = 0; i < n; ++i) {
+            const ItemBufs& b = bufs[(size_t)i];
+            for (const Buf* x : {&b.in, &b.mid, &b.out, &b.work})
+                if (x->base && (uintptr_t)p >= x->base && (uintptr_t)p < x->base + x->bytes) return i;
         }
-        if (f[e - b] != tab.queue_tickets[(size_t)q]) return fail("queue total");
-        all += f[e - b];
+        return -1;
+    };
+    // 1. the table
+    if (tab.levels) {
+        // level mode: every launch of one kind and dtype, its first-tile table
+        // counting its tasks' tiles; every item's passes those of the
+        // persistent table of the same items, in the same order, each in a
+        // later launch than the one before
+        const int nl = (int)tab.launches.size();
+        if ((int)tab.firsts.size() != nt + nl) return fail("levels: first-tile table size");
+        int64_t all = 0;
+        int next_task = 0;
+        std::vector<std::vector<std::pair<int, int>>> got((size_t)n);
+        for (int j = 0; j < nl; ++j) {
+            const BatchLaunch& L = tab.launches[(size_t)j];
+            if (L.ntasks < 1 || L.task_begin != next_task) return fail("levels: launch task ranges");
+            for (int d : L.deps)
+                if (d < 0 || d >= j) return fail("levels: a launch depends on a later one");
+            next_task += L.ntasks;
+            const int32_t* f = tab.firsts.data() + L.firsts_begin;
+            if (L.firsts_begin != L.task_begin + j || f[0] != 0) return fail("levels: first-tile table layout");
+            for (int k = L.task_begin; k < L.task_begin + L.ntasks; ++k) {
+                const BatchTask& t = tab.tasks[(size_t)k];
+                if (t.kind != L.kind || t.f64 != L.f64) return fail("levels: a launch mixes kinds or dtypes");
+                if (t.ntiles < 1 || f[k - L.task_begin + 1] - f[k - L.task_begin] != t.ntiles)
+                    return fail("levels: first-tile table does not count tiles");
+                if ((size_t)t.lds > L.lds || (int64_t)L.lds > kBatchLdsCap) return fail("levels: LDS over budget");
+                const int item = owner_of(t.in);
+                if (item < 0) return fail("levels: task of no item");
+                got[(size_t)item].push_back({j, k});
+            }
+            if (f[L.ntasks] != L.tiles) return fail("levels: launch tiles");
+            all += L.tiles;
+        }
+        if (next_task != nt || all != tab.tickets) return fail("levels: task or tile totals");
+        BatchOptions o2 = o;
+        o2.mode = 4;
+        BatchTable ref;
+        if (const char* why = build_batch_table(specs.data(), n, o2, ref)) return fail(why);
+        std::vector<int> lvl(ref.tasks.size(), 0);
+        std::vector<std::vector<int>> chain((size_t)n);
+        for (size_t k = 0; k < ref.tasks.size(); ++k) {
+            const BatchTask& t = ref.tasks[k];
+            if (t.dep >= 0) lvl[k] = lvl[(size_t)t.dep] + 1;
+            std::vector<int>& c = chain[(size_t)owner_of(t.in)];
+            if ((int)c.size() <= lvl[k]) c.resize((size_t)lvl[k] + 1, -1);
+            c[(size_t)lvl[k]] = (int)k;
+        }
+        for (int i = 0; i < n; ++i) {
+            const std::vector<int>& c = chain[(size_t)i];
+            const auto& g = got[(size_t)i];
+            if (g.size() != c.size()) return fail("levels: item " + std::to_string(i) + " has a different pass count");
+            for (size_t L = 0; L < c.size(); ++L) {
+                const BatchTask& a = tab.tasks[(size_t)g[L].second];
+                const BatchTask& b = ref.tasks[(size_t)c[L]];
+                if (a.kind != b.kind || a.in != b.in || a.out != b.out || a.ntiles != b.ntiles || a.a0 != b.a0)
+                    return fail("levels: item " + std::to_string(i) + " pass " + std::to_string(L) + " differs");
+                if (L > 0 && g[L].first <= g[L - 1].first)
+                    return fail("levels: item " + std::to_string(i) + " pass " + std::to_string(L) +
+                                " not in a later launch than its predecessor");
+                if (L > 0) {
+                    const std::vector<int>& d = tab.launches[(size_t)g[L].first].deps;
+                    if (std::find(d.begin(), d.end(), g[L - 1].first) == d.end())
+                        return fail("levels: a launch does not depend on its tasks' predecessors' launch");
+                }
+            }
+        }
+    } else {
+        if ((int)tab.task_begin.size() != nq + 1 || tab.task_begin[0] != 0 || tab.task_begin[(size_t)nq] != nt)
+            return fail("queue task ranges");
+        if ((int)tab.firsts.size() != nt + nq) return fail("ticket table size");
+        std::vector<int> qof((size_t)nt, -1);
+        int64_t all = 0;
+        for (int q = 0; q < nq; ++q) {
+            const int b = tab.task_begin[(size_t)q], e = tab.task_begin[(size_t)q + 1];
+            const int32_t* f = tab.firsts.data() + b + q;
+            if (f[0] != 0) return fail("queue tickets do not start at 0");
+            for (int k = b; k < e; ++k) {
+                qof[(size_t)k] = q;
+                const BatchTask& t = tab.tasks[(size_t)k];
+                if (t.ntiles < 1) return fail("empty task");
+                if (f[k - b + 1] - f[k - b] != t.ntiles) return fail("ticket table does not count tiles");
+                if (t.dep >= 0 && (t.dep < b || t.dep >= k)) return fail("task waits for a later task or another queue");
+                if (t.dep >= 0 && t.dep_tiles != tab.tasks[(size_t)t.dep].ntiles) return fail("dep_tiles");
+                if ((size_t)t.lds > tab.lds || (int64_t)tab.lds > kBatchLdsCap) return fail("LDS over budget");
+            }
+            if (f[e - b] != tab.queue_tickets[(size_t)q]) return fail("queue total");
+            all += f[e - b];
+        }
+        if (all != tab.tickets) return fail("ticket total");
+        if (tab.pinned ? nq != xcds : nq != 1) return fail("queue count");
+        for (int x = 0; x < xcds; ++x)
+            if (tab.qmap[x] < 0 || tab.qmap[x] >= nq) return fail("an XCD without a queue");
     }
-    if (all != tab.tickets) return fail("ticket total");
-    if (tab.pinned ? nq != xcds : nq != 1) return fail("queue count");
-    for (int x = 0; x < xcds; ++x)
-        if (tab.qmap[x] < 0 || tab.qmap[x] >= nq) return fail("an XCD without a queue");
 
     // 2. tile footprints against the buffers of the item that owns the task
     auto owner = [&](const void* p) -> int {
@@ -296,6 +382,12 @@ int main(int argc, char** argv)
             }
             if (!good) return fail("task " + std::to_string(k) + " tile " + std::to_string(tile) + " outside its buffers");
         }
+    }
+
+    if (tab.levels) {
+        // stream order is the level mode's only synchronisation: nothing to run
+        printf("ok levels %d %d %lld %zu\n", nt, (int)tab.launches.size(), (long long)tab.tickets, tab.lds);
+        return 0;
     }
 
     // 3. the ticket protocol on G threads

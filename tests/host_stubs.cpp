@@ -63,12 +63,15 @@ hipError_t init_batch() { return hipErrorNotSupported; }
 const void* batch_kernel() { return nullptr; }
 hipError_t batch_occupancy(size_t, int*) { return hipErrorNotSupported; }
 hipError_t launch_batch(unsigned, size_t, const void*, int*, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t probe_xcc_ids(int, int*) { return hipErrorNotSupported; }
-hipError_t static_scratch_setup(int) { return hipErrorNotSupported; }
-void* static_scratch(int) { return nullptr; }
-hipError_t launch_static_batch(int, const void*, size_t, int, unsigned, size_t, int*, hipStream_t)
+hipError_t init_level() { return hipErrorNotSupported; }
+const void* level_kernel(int, int) { return nullptr; }
+hipError_t launch_level(int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
 {
     return hipErrorNotSupported;
 }
+hipError_t probe_xcc_ids(int, int*) { return hipErrorNotSupported; }
+hipError_t static_scratch_setup(int) { return hipErrorNotSupported; }
+void* static_scratch(int) { return nullptr; }
+hipError_t stage_static_image(int, const void*, size_t, const void**, hipStream_t) { return hipErrorNotSupported; }
 
 }  // namespace fft3d

@@ -151,3 +151,37 @@ def test_spin_limit_error_path(sim):
     p = subprocess.run([sim.exe, "16"], input="spin 1000000\n" + "\n".join(items) + "\n", capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 0 and p.stdout.startswith("ok"), p.stdout + p.stderr
+
+
+def run_levels(sim, lines):
+    p = subprocess.run([sim.exe, "1"], input="mode 3\n" + "\n".join(lines) + "\n", capture_output=True, text=True,
+                       timeout=120)
+    out = p.stdout.strip()
+    assert p.returncode == 0 and out.startswith("ok levels"), out + p.stderr
+    _, _, tasks, launches, tiles, lds = out.split()
+    return int(tasks), int(launches), int(tiles), int(lds)
+
+
+def test_level_mode_schedules(sim):
+    """Level mode (one launch per pass level, tile kind and dtype): every
+    launch holds one kind and dtype, every item's passes are those of the
+    persistent table in the same order, each in a later launch than the pass
+    it reads, and every tile stays inside its item's buffers."""
+    mix = fields.batch_mix(64, seed=4)
+    tasks, launches, tiles, lds = run_levels(sim, [item(s, d, 2) for s, d in mix])
+    assert tasks >= 4 * 64 and tiles > 0 and lds <= 80 * 1024 - 256
+    # round trips of fused and split items: at most 8 launches per dtype
+    assert launches <= 16
+    shapes = [(1, 1, 2), (2, 3, 4), (1, 8, 16), (8, 1, 8), (12, 9, 24), (96, 96, 96), (192, 192, 96),
+              (256, 256, 256), (8, 512, 512), (1024, 2, 2), (4, 16, 4096), (729, 4, 6)]
+    lines = [item(s, d, i % 3, work=(i // 3) % 2) for i, s in enumerate(shapes) for d in ("f32", "f64")]
+    run_levels(sim, lines)
+    rng = np.random.default_rng(9)
+    ext = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128]
+    for trial in range(6):
+        lines = []
+        for _ in range(int(rng.integers(1, 40))):
+            n0, n1 = (int(rng.choice(ext)) for _ in range(2))
+            lines.append(item((n0, n1, 2 * int(rng.choice(ext))), ("f32", "f64")[int(rng.integers(2))],
+                              int(rng.integers(3)), int(rng.integers(2))))
+        run_levels(sim, lines)

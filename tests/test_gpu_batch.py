@@ -127,19 +127,22 @@ def test_mixed_batch_matches_alone_and_oracle(F, oracle):
         assert e1 <= TOL[it.dtype] and e2 <= TOL[it.dtype], (key, e1, e2)
 
 
+@pytest.mark.parametrize("mode", [0, 4], ids=["levels", "persistent"])
 @pytest.mark.parametrize("flags", [0, 4], ids=["graph", "direct"])
-def test_batch_handle_replays(F, flags):
+def test_batch_handle_replays(F, flags, mode):
     """A batch handle launched three times (graph replays, or direct launches)
-    with unrelated device work in between: every launch bit-identical to the
-    items alone, status clean."""
+    with unrelated device work in between, in level mode (the rule) and as
+    the persistent launch: every launch bit-identical to the items alone,
+    status clean."""
     import torch
     mix = [((32, 32, 32), "f64"), ((48, 48, 48), "f32"), ((96, 96, 96), "f64"), ((64, 64, 64), "f32"),
            ((128, 128, 128), "f32"), ((192, 192, 96), "f64")]
-    say("batch handle flags=%d" % flags)
+    say("batch handle flags=%d mode=%d" % (flags, mode))
     items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 2000 + i) for i, (s, d) in enumerate(mix)]
-    b = F.Batch([it.tuple() for it in items], flags)
+    b = F.Batch([it.tuple() for it in items], flags, tuning={"mode": mode})
     desc = b.describe()
     assert desc["items"] == len(items) and desc["graph"] == (flags == 0)
+    assert (desc["mode"] == "levels") == (mode == 0)
     assert len(desc["tasks"]) >= 4 * len(items) and desc["tickets"] > 0
     junk = torch.randn(1 << 20, device="cuda")
     for rep in range(3):
@@ -207,14 +210,15 @@ def test_ticket_orders_give_same_bits(F, lag, mode):
     assert b.status() == 0
 
 
-@pytest.mark.parametrize("widen,wg", [(2, 0), (1, 1), (2, 1)])
-def test_batch_tile_shapes_give_same_bits(F, widen, wg):
-    """The plans' own tile shapes instead of widened ones, and one workgroup
-    per CU: same bits."""
+@pytest.mark.parametrize("widen,wg,mode", [(2, 0, 0), (2, 0, 4), (1, 1, 4), (2, 1, 4)])
+def test_batch_tile_shapes_give_same_bits(F, widen, wg, mode):
+    """The plans' own tile shapes instead of widened ones (level mode and
+    persistent), and one workgroup per CU (persistent): same bits."""
     mix = fields.batch_mix(10, seed=17)
-    say("batch: widen %d wg_per_cu %d" % (widen, wg))
+    say("batch: widen %d wg_per_cu %d mode %d" % (widen, wg, mode))
     items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 5500 + i) for i, (s, d) in enumerate(mix)]
-    b = F.Batch([it.tuple() for it in items], flags=F.FFT3D_BATCH_DIRECT, tuning={"widen": widen, "wg_per_cu": wg})
+    b = F.Batch([it.tuple() for it in items], flags=F.FFT3D_BATCH_DIRECT,
+                tuning={"widen": widen, "wg_per_cu": wg, "mode": mode})
     b.launch()
     _sync()
     for it in items:
@@ -222,17 +226,55 @@ def test_batch_tile_shapes_give_same_bits(F, widen, wg):
     assert b.status() == 0
 
 
+@pytest.mark.parametrize("flags", [0, 4], ids=["graph", "direct"])
+def test_level_mode_gives_same_bits(F, flags):
+    """Level mode (batch tuning mode 3: one launch per pass level, tile kind
+    and dtype, in one graph or launched directly): the 64-field mix, the
+    retiled big items and every direction and work mode, bit-identical to the
+    items alone, three launches in a row with unrelated device work between
+    them; status 0."""
+    import torch
+    R, C, T = F.FFT3D_R2C, F.FFT3D_C2R, F.FFT3D_ROUNDTRIP
+    specs = [(s, d, T, True) for s, d in fields.batch_mix(64, seed=4)]
+    specs += [(s, d, T, True) for s, d in BIG_ALONE[:6]]
+    specs += [((32, 32, 32), "f64", R, True), ((48, 36, 64), "f32", C, True), ((64, 64, 64), "f64", C, False),
+              ((96, 64, 32), "f32", T, False), ((12, 9, 24), "f64", T, True), ((1, 8, 16), "f32", R, True),
+              ((8, 1, 8), "f64", C, True), ((1, 1, 2), "f32", T, True)]
+    say("batch: level mode flags=%d, %d items" % (flags, len(specs)))
+    items = [Item(F, s, d, r, 9100 + i, work=w) for i, (s, d, r, w) in enumerate(specs)]
+    b = F.Batch([it.tuple() for it in items], flags=flags, tuning={"mode": 3})
+    desc = b.describe()
+    assert desc["mode"] == "levels" and desc["graph"] == (flags == 0)
+    launches = desc["launches"]
+    assert launches and sum(L[2] for L in launches) == len(desc["tasks"])
+    assert sum(L[3] for L in launches) == desc["tickets"]
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        for it in items:
+            it.reset()
+        junk.mul_(1.0001).add_(0.5)
+        b.launch()
+        _sync()
+        for it in items:
+            it.check_bits()
+            if it.dir == C and it.work is not None:
+                assert bool((it.inp == it.X0).all()), "C2R with work modified its input"
+        assert b.status() == 0
+    b.close()
+
+
 def test_wait_error_path_ends_the_launch(F):
-    """Dependency waits that give up at once (batch tuning spin_limit < 0, no
-    poll): every second pass of an item fails its wait, its tiles are
-    skipped, and the launch still ends with error bit 1 -- twice in a row on
-    the same handle (the last workgroup clears the counters either way).  A
-    handle with the rule then computes the same items correctly."""
+    """The persistent launch (mode 4) with dependency waits that give up at
+    once (batch tuning spin_limit < 0, no poll): every second pass of an item
+    fails its wait, its tiles are skipped, and the launch still ends with
+    error bit 1 -- twice in a row on the same handle (the last workgroup
+    clears the counters either way).  A handle with the rule then computes
+    the same items correctly."""
     mix = fields.batch_mix(8, seed=23)
     say("batch: wait error path")
     items = [Item(F, s, d, F.FFT3D_ROUNDTRIP, 8300 + i) for i, (s, d) in enumerate(mix)]
     for flags in (0, F.FFT3D_BATCH_DIRECT):
-        b = F.Batch([it.tuple() for it in items], flags=flags, tuning={"spin_limit": -1})
+        b = F.Batch([it.tuple() for it in items], flags=flags, tuning={"spin_limit": -1, "mode": 4})
         for _ in range(2):
             b.launch()
             _sync()

@@ -2,7 +2,7 @@
 (fft3d_batch_submit_static): the same items through it and through
 fft3d_batch_submit must give bit-identical outputs, on two calls in a row
 (the second with a smaller batch, so the static array holds the first call's
-task image and counters when the second starts), with clean error bits; a
+task image when the second starts), with clean error bits; a
 batch beyond the array's limit is refused with nothing enqueued."""
 import numpy as np
 import pytest
