@@ -496,13 +496,18 @@ __device__ __forceinline__ void plane_c2r_tile(const cx<T>* Xi, cx<T>* yz, int n
     fft_lines<true, false, NT, EPT, T>(lr, lr, go, rows, 0u, axh, tw2);
 }
 
-// Fused plane kernels: ppw whole planes per workgroup.
+// Fused plane kernels: ppw whole planes per workgroup.  Their pointer
+// arguments are not declared restrict: with it the compiler keeps more of the
+// tables in registers across both axes' stages (163 VGPRs instead of 113 for
+// the FP32 small tier, one workgroup a CU instead of two; the big tier
+// spilled); measured without it: 96^3 FP64 and 192x192x96 FP32 plane steps
+// 11% and 24% faster, the others equal, bits unchanged.
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axhp,
-                                                  const AxisSched* __restrict__ ax1p,
-                                                  const cx<T>* __restrict__ tw2,
-                                                  const cx<T>* __restrict__ post,
-                                                  const cx<T>* __restrict__ tw1, int64_t nplanes,
+__global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const AxisSched* axhp,
+                                                  const AxisSched* ax1p,
+                                                  const cx<T>* tw2,
+                                                  const cx<T>* post,
+                                                  const cx<T>* tw1, int64_t nplanes,
                                                   int ppw, int Hs, uint32_t mg_lines, uint32_t mgH, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -516,11 +521,11 @@ __global__ __launch_bounds__(NT) void k_plane_r2c(const T* x, cx<T>* X, const Ax
 }
 
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const AxisSched* __restrict__ axhp,
-                                                  const AxisSched* __restrict__ ax1p,
-                                                  const cx<T>* __restrict__ tw2,
-                                                  const cx<T>* __restrict__ post,
-                                                  const cx<T>* __restrict__ tw1, int64_t nplanes,
+__global__ __launch_bounds__(NT) void k_plane_c2r(const cx<T>* X, T* y, const AxisSched* axhp,
+                                                  const AxisSched* ax1p,
+                                                  const cx<T>* tw2,
+                                                  const cx<T>* post,
+                                                  const cx<T>* tw1, int64_t nplanes,
                                                   int ppw, int Hs, uint32_t mg_lines, uint32_t mgH, int rs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];

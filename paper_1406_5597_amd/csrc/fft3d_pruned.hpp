@@ -235,12 +235,14 @@ __global__ __launch_bounds__(NT, (rows_waves<T, EPT, true>())) void k_rows_c2r_p
     fft_lines<true, false, NT, EPT, T>(l, l, g, rows, 0u, axh, tw);
 }
 
-// Fused plane step, forward: the n1 columns write the kept box only.
+// Fused plane step, forward: the n1 columns write the kept box only.  (No
+// restrict on the pointer arguments, as for the full fused plane kernels:
+// fewer registers, no spills in the big tier.)
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_plane_r2c_pr(const T* x, cx<T>* X, const AxisSched* __restrict__ axhp,
-                                                     const AxisSched* __restrict__ ax1p,
-                                                     const cx<T>* __restrict__ tw2, const cx<T>* __restrict__ post,
-                                                     const cx<T>* __restrict__ tw1, int64_t nplanes, int ppw, int Hs,
+__global__ __launch_bounds__(NT) void k_plane_r2c_pr(const T* x, cx<T>* X, const AxisSched* axhp,
+                                                     const AxisSched* ax1p,
+                                                     const cx<T>* tw2, const cx<T>* post,
+                                                     const cx<T>* tw1, int64_t nplanes, int ppw, int Hs,
                                                      uint32_t mg_lines, uint32_t mgH, int K1, int K2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -274,10 +276,10 @@ __global__ __launch_bounds__(NT) void k_plane_r2c_pr(const T* x, cx<T>* X, const
 
 // Fused plane step, inverse: the n1 columns read the kept box only.
 template <typename T, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_plane_c2r_pr(const cx<T>* X, T* y, const AxisSched* __restrict__ axhp,
-                                                     const AxisSched* __restrict__ ax1p,
-                                                     const cx<T>* __restrict__ tw2, const cx<T>* __restrict__ post,
-                                                     const cx<T>* __restrict__ tw1, int64_t nplanes, int ppw, int Hs,
+__global__ __launch_bounds__(NT) void k_plane_c2r_pr(const cx<T>* X, T* y, const AxisSched* axhp,
+                                                     const AxisSched* ax1p,
+                                                     const cx<T>* tw2, const cx<T>* post,
+                                                     const cx<T>* tw1, int64_t nplanes, int ppw, int Hs,
                                                      uint32_t mg_lines, uint32_t mgH, int K1, int K2)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
