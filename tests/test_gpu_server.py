@@ -169,3 +169,43 @@ def test_server_radix57_and_odd_n2_requests(F):
             srv.release(rid)
         st = srv.stats()
     assert st["batched_launches"] >= 1
+
+
+def test_server_large_requests(F, oracle):
+    """Requests at the sizes of the served workload's large end (256^3 and
+    512^3 FP32, 256x256x128 FP64; forward and inverse), served alone under
+    the budget: bit for bit the transforms run alone, and sampled outputs of
+    the 512^3 request against the oracle's point evaluator."""
+    import torch
+    say("server: large requests")
+    specs = [((256, 256, 256), "f32", F.FFT3D_R2C, 3), ((256, 256, 256), "f32", F.FFT3D_C2R, 3),
+             ((256, 256, 128), "f64", F.FFT3D_C2R, 2), ((512, 512, 512), "f32", F.FFT3D_R2C, 1)]
+    with F.Server(6 << 30, nstreams=2, batch_points=1 << 20) as srv:
+        for i, (s, d, r, nc) in enumerate(specs):
+            p = F.Plan(*s, dtype=d)
+            xs = [dev_real(fields.as_dtype(fields.uniform(s, 700 + 5 * i + c), d), d) for c in range(nc)]
+            if r == F.FFT3D_R2C:
+                ins = xs
+                want = [F.r2c(p, x) for x in xs]
+            else:
+                ins = [F.r2c(p, x) for x in xs]
+                want = [F.c2r(p, X.clone(), work=F.empty_complex(p)) for X in ins]
+            torch.cuda.synchronize()
+            rid = srv.submit(s, d, r, ins)
+            assert srv.wait(rid, 60.0)
+            outs, _ = srv.result(rid, nc)
+            for c in range(nc):
+                got = torch.empty_like(want[c])
+                F.copy_from_device(got, outs[c], got.numel() * got.element_size())
+                assert bool((got == want[c]).all()), (s, d, r, c)
+            if s == (512, 512, 512):
+                x = host(xs[0]).astype(np.float64)
+                Xg = host(got)
+                scale = np.sqrt(np.sum(x * x))  # the same bound as the sampled parity tests
+                for k in [(0, 0, 0), (3, 511, 17), (256, 100, 256), (511, 1, 1)]:
+                    ref = oracle.r2c_point(x, k)
+                    assert abs(Xg[k] - ref) / scale <= 5e-6, (k, Xg[k], ref)
+            srv.release(rid)
+            del xs, ins, want
+        st = srv.stats()
+    assert st["completed"] == len(specs) and st["reserved_bytes"] == 0
