@@ -838,7 +838,7 @@ int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, co
             void* params[] = {&a.tasks, &a.firsts, &a.ntasks};
             hipKernelNodeParams kp;
             memset(&kp, 0, sizeof kp);
-            kp.func = const_cast<void*>(fft3d::level_kernel(L.kind, L.f64));
+            kp.func = const_cast<void*>(fft3d::level_kernel(L.kind, L.f64, L.big));
             kp.gridDim = dim3((unsigned)L.tiles);
             kp.blockDim = dim3(fft3d::kNtSmall);
             kp.sharedMemBytes = (unsigned)L.lds;

@@ -28,7 +28,7 @@ enum BatchKind : int32_t {
 struct BatchTask {
     int32_t kind;    // BatchKind
     int32_t f64;     // 1: FP64 data and tables, 0: FP32
-    int32_t pad0_;
+    int32_t big;     // 1: a big-tier fused plane tile (level mode only), 0: small tier
     int32_t ntiles;  // tiles of this task
     int32_t dep;     // task this one waits for, or -1
     int32_t dep_tiles;
@@ -119,8 +119,8 @@ hipError_t launch_batch(unsigned grid, size_t lds, const void* image, int* ctr, 
 // and one launch of it over `ntasks` tasks (device pointers: the tasks, and
 // the first tile of each) with one workgroup per tile (grid = total tiles).
 hipError_t init_level();
-const void* level_kernel(int kind, int f64);
-hipError_t launch_level(int kind, int f64, unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts,
+const void* level_kernel(int kind, int f64, int big);
+hipError_t launch_level(int kind, int f64, int big, unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts,
                         int ntasks, hipStream_t s);
 // Hardware XCC id of every workgroup of a `blocks`-block probe launch
 // (synchronous; `ids` gets `blocks` values).

@@ -44,6 +44,7 @@ int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 // arithmetic of every line is the same, so the bits are too.
 struct ItemTiling {
     bool fused = false;
+    bool plane_big = false;  // the plan's own big-tier fused plane tile (level mode)
     size_t plane_lds = 0;
     int ppw = 1;
     int rpw = 1;
@@ -70,13 +71,22 @@ void widen_cols(ColPass& cp, int64_t n, const Plan& p)
     cp.lds = (size_t)(n * cp.W * cxs);
 }
 
-const char* item_tiling(const Plan& p, bool widen, ItemTiling& t)
+// big_planes: a plane that needs the big tier keeps its fused tile (the
+// level mode has a kernel for it) instead of taking the split step.
+const char* item_tiling(const Plan& p, bool widen, bool big_planes, ItemTiling& t)
 {
     if (p.n0 > 1) {
         t.pass0 = p.pass0;
         if ((t.pass0.big || t.pass0.wide) && !small_colpass(p, 0, t.pass0))
             return "n0 too long for a small-tier column tile";
         if (widen) widen_cols(t.pass0, p.n0, p);
+    }
+    if (p.fused_plane && p.plane_big && big_planes) {
+        t.fused = true;
+        t.plane_big = true;
+        t.plane_lds = p.plane_lds;
+        t.ppw = p.ppw;
+        return nullptr;
     }
     if (p.fused_plane && !p.plane_big && p.plane_lds <= kBatchLdsCap) {
         t.fused = true;
@@ -151,6 +161,7 @@ void add_plane(std::vector<BatchTask>& chain, const Plan& p, const ItemTiling& p
     t.t1 = tw_at(p, p.off_post);
     t.t2 = tw_at(p, p.off_ax1);
     t.lds = (int32_t)(pt.ppw * pt.plane_lds);
+    t.big = pt.plane_big ? 1 : 0;
     chain.push_back(t);
 }
 
@@ -222,7 +233,7 @@ const char* build_levels(const std::vector<std::vector<BatchTask>>& chains, cons
                          BatchTable& tab)
 {
     struct Group {
-        int kind, f64;
+        int kind, f64, big;
         std::vector<const BatchTask*> tasks;
         std::vector<const BatchTask*> preds;  // the pass before each task (or null)
     };
@@ -239,10 +250,12 @@ const char* build_levels(const std::vector<std::vector<BatchTask>>& chains, cons
         const BatchTask* pred = nullptr;
         for (const BatchTask& t : chains[(size_t)i]) {
             int j = prev + 1;
-            while (j < (int)g.size() && !(g[(size_t)j].kind == t.kind && g[(size_t)j].f64 == t.f64)) ++j;
+            while (j < (int)g.size() &&
+                   !(g[(size_t)j].kind == t.kind && g[(size_t)j].f64 == t.f64 && g[(size_t)j].big == t.big))
+                ++j;
             if (j == (int)g.size()) {
                 j = prev + 1;
-                g.insert(g.begin() + j, Group{t.kind, t.f64, {}, {}});
+                g.insert(g.begin() + j, Group{t.kind, t.f64, t.big, {}, {}});
             }
             g[(size_t)j].tasks.push_back(&t);
             g[(size_t)j].preds.push_back(pred);
@@ -268,6 +281,7 @@ const char* build_levels(const std::vector<std::vector<BatchTask>>& chains, cons
                          [](const BatchTask* a, const BatchTask* b) { return a->ntiles > b->ntiles; });
         L.kind = gr.kind;
         L.f64 = gr.f64;
+        L.big = gr.big;
         L.task_begin = (int)tab.tasks.size();
         L.ntasks = (int)gr.tasks.size();
         L.firsts_begin = (int)tab.firsts.size();
@@ -304,7 +318,8 @@ const char* build_batch_table(const BatchSpec* items, int n, const BatchOptions&
         const BatchSpec& it = items[i];
         const Plan& p = *it.plan;
         ItemTiling pt;
-        if (const char* why = item_tiling(p, o.widen, pt)) return why;
+        const bool levels = o.mode == 0 || o.mode == 3;
+        if (const char* why = item_tiling(p, o.widen, levels, pt)) return why;
         std::vector<BatchTask>& c = chains[(size_t)i];
         switch (it.dir) {
         case FFT3D_R2C: chain_r2c(c, p, pt, it.in, it.out); break;
@@ -476,7 +491,7 @@ hipError_t enqueue_batch_image(const BatchTable& tab, unsigned grid, const void*
         const BatchTask* tasks = reinterpret_cast<const BatchTask*>(static_cast<const char*>(dev_image) +
                                                                     level_tasks_offset(tab));
         for (const BatchLaunch& L : tab.launches) {
-            const hipError_t e = launch_level(L.kind, L.f64, (unsigned)L.tiles, L.lds, tasks + L.task_begin,
+            const hipError_t e = launch_level(L.kind, L.f64, L.big, (unsigned)L.tiles, L.lds, tasks + L.task_begin,
                                               firsts + L.firsts_begin, L.ntasks, s);
             if (e != hipSuccess) return e;
         }

@@ -46,6 +46,7 @@ struct BatchOptions {
 struct BatchLaunch {
     int kind = 0;
     int f64 = 0;
+    int big = 0;  // big-tier fused plane tiles
     int task_begin = 0;
     int ntasks = 0;
     int firsts_begin = 0;

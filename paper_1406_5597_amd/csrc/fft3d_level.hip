@@ -26,8 +26,10 @@ template <typename T, int K> constexpr int level_waves()
 
 // Workgroup b runs tile b - firsts[i] of task i, the last task with
 // firsts[i] <= b (firsts: the first tile of each of the launch's ntasks
-// tasks, ascending; the grid is the launch's total tiles).
-template <typename T, int K>
+// tasks, ascending; the grid is the launch's total tiles).  BIG: the tiles
+// are big-tier fused planes (the plan's own tile for planes of more than
+// the small tier's elements; up to the whole LDS).
+template <typename T, int K, bool BIG>
 __global__ __launch_bounds__(kNtSmall, (level_waves<T, K>())) void k_level(const BatchTask* __restrict__ tasks,
                                                                            const int* __restrict__ firsts,
                                                                            int ntasks)
@@ -40,44 +42,55 @@ __global__ __launch_bounds__(kNtSmall, (level_waves<T, K>())) void k_level(const
         if (firsts[mid] <= b) lo = mid;
         else hi = mid;
     }
-    batch_tile_kind<T, Tier<T>::kEptSmall, K>(rebased(tasks[lo], tasks), b - firsts[lo], smem_raw);
+    constexpr int EPT = BIG ? Tier<T>::kEptBig : Tier<T>::kEptSmall;
+    batch_tile_kind<T, EPT, K>(rebased(tasks[lo], tasks), b - firsts[lo], smem_raw);
 }
 
 namespace {
 
-template <typename T> const void* level_kernel_t(int kind)
+template <typename T> const void* level_kernel_t(int kind, bool big)
 {
+    if (big) {
+        if (kind == kBkPlaneR2C) return reinterpret_cast<const void*>(&k_level<T, kBkPlaneR2C, true>);
+        if (kind == kBkPlaneC2R) return reinterpret_cast<const void*>(&k_level<T, kBkPlaneC2R, true>);
+        return nullptr;  // big tiles are fused planes only
+    }
     switch (kind) {
-    case kBkPlaneR2C: return reinterpret_cast<const void*>(&k_level<T, kBkPlaneR2C>);
-    case kBkPlaneC2R: return reinterpret_cast<const void*>(&k_level<T, kBkPlaneC2R>);
-    case kBkRowsR2C: return reinterpret_cast<const void*>(&k_level<T, kBkRowsR2C>);
-    case kBkRowsC2R: return reinterpret_cast<const void*>(&k_level<T, kBkRowsC2R>);
-    case kBkColsFwd: return reinterpret_cast<const void*>(&k_level<T, kBkColsFwd>);
-    case kBkColsInv: return reinterpret_cast<const void*>(&k_level<T, kBkColsInv>);
+    case kBkPlaneR2C: return reinterpret_cast<const void*>(&k_level<T, kBkPlaneR2C, false>);
+    case kBkPlaneC2R: return reinterpret_cast<const void*>(&k_level<T, kBkPlaneC2R, false>);
+    case kBkRowsR2C: return reinterpret_cast<const void*>(&k_level<T, kBkRowsR2C, false>);
+    case kBkRowsC2R: return reinterpret_cast<const void*>(&k_level<T, kBkRowsC2R, false>);
+    case kBkColsFwd: return reinterpret_cast<const void*>(&k_level<T, kBkColsFwd, false>);
+    case kBkColsInv: return reinterpret_cast<const void*>(&k_level<T, kBkColsInv, false>);
     default: return nullptr;
     }
 }
 
 }  // namespace
 
-const void* level_kernel(int kind, int f64) { return f64 ? level_kernel_t<double>(kind) : level_kernel_t<float>(kind); }
+const void* level_kernel(int kind, int f64, int big)
+{
+    return f64 ? level_kernel_t<double>(kind, big != 0) : level_kernel_t<float>(kind, big != 0);
+}
 
 hipError_t init_level()
 {
     hipError_t e = hipSuccess;
     for (int f64 = 0; f64 < 2; ++f64)
-        for (int kind = kBkPlaneR2C; kind <= kBkColsInv; ++kind) {
-            const hipError_t r = hipFuncSetAttribute(level_kernel(kind, f64),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
-            if (r != hipSuccess) e = r;
-        }
+        for (int big = 0; big < 2; ++big)
+            for (int kind = kBkPlaneR2C; kind <= kBkColsInv; ++kind) {
+                const void* f = level_kernel(kind, f64, big);
+                if (!f) continue;
+                const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+                if (r != hipSuccess) e = r;
+            }
     return e;
 }
 
-hipError_t launch_level(int kind, int f64, unsigned grid, size_t lds, const BatchTask* tasks, const int* firsts,
-                        int ntasks, hipStream_t s)
+hipError_t launch_level(int kind, int f64, int big, unsigned grid, size_t lds, const BatchTask* tasks,
+                        const int* firsts, int ntasks, hipStream_t s)
 {
-    const void* f = level_kernel(kind, f64);
+    const void* f = level_kernel(kind, f64, big);
     if (!f || grid == 0 || ntasks < 1) return hipErrorInvalidValue;
     void* args[] = {&tasks, &firsts, &ntasks};
     return hipLaunchKernel(f, dim3(grid), dim3(kNtSmall), args, lds, s);

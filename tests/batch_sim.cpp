@@ -65,7 +65,7 @@ hipError_t batch_occupancy(size_t, int* per_cu)
     return hipSuccess;
 }
 hipError_t launch_batch(unsigned, size_t, const void*, int*, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_level(int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
+hipError_t launch_level(int, int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
 {
     return hipErrorNotSupported;
 }
@@ -243,7 +243,9 @@ int main(int argc, char** argv)
                 if (t.kind != L.kind || t.f64 != L.f64) return fail("levels: a launch mixes kinds or dtypes");
                 if (t.ntiles < 1 || f[k - L.task_begin + 1] - f[k - L.task_begin] != t.ntiles)
                     return fail("levels: first-tile table does not count tiles");
-                if ((size_t)t.lds > L.lds || (int64_t)L.lds > kBatchLdsCap) return fail("levels: LDS over budget");
+                if ((size_t)t.lds > L.lds || (int64_t)L.lds > (L.big ? kLdsMax : kBatchLdsCap))
+                    return fail("levels: LDS over budget");
+                if (t.big != L.big) return fail("levels: a launch mixes tiers");
                 const int item = owner_of(t.in);
                 if (item < 0) return fail("levels: task of no item");
                 got[(size_t)item].push_back({j, k});
@@ -252,37 +254,63 @@ int main(int argc, char** argv)
             all += L.tiles;
         }
         if (next_task != nt || all != tab.tickets) return fail("levels: task or tile totals");
-        BatchOptions o2 = o;
-        o2.mode = 4;
-        BatchTable ref;
-        if (const char* why = build_batch_table(specs.data(), n, o2, ref)) return fail(why);
-        std::vector<int> lvl(ref.tasks.size(), 0);
-        std::vector<std::vector<int>> chain((size_t)n);
-        for (size_t k = 0; k < ref.tasks.size(); ++k) {
-            const BatchTask& t = ref.tasks[k];
-            if (t.dep >= 0) lvl[k] = lvl[(size_t)t.dep] + 1;
-            std::vector<int>& c = chain[(size_t)owner_of(t.in)];
-            if ((int)c.size() <= lvl[k]) c.resize((size_t)lvl[k] + 1, -1);
-            c[(size_t)lvl[k]] = (int)k;
-        }
+        // each item's passes, in launch order, are the chain the single-item
+        // path runs: the plane step (fused, or rows + n1 columns) and the n0
+        // columns, reversed for the inverse; each pass reads what the pass
+        // before wrote, from the item's input to its output; each is in a
+        // later launch than the pass before, and that launch is among its
+        // launch's dependencies
         for (int i = 0; i < n; ++i) {
-            const std::vector<int>& c = chain[(size_t)i];
             const auto& g = got[(size_t)i];
-            if (g.size() != c.size()) return fail("levels: item " + std::to_string(i) + " has a different pass count");
-            for (size_t L = 0; L < c.size(); ++L) {
+            const Plan& p = plans[(size_t)i];
+            const ItemBufs& bb = bufs[(size_t)i];
+            const int dir = dirs[(size_t)i];
+            const std::string who = "levels: item " + std::to_string(i);
+            std::vector<std::pair<int, int>> want;  // (kind, column axis or -1)
+            size_t at = 0;
+            auto kind_at = [&](size_t L) { return L < g.size() ? tab.tasks[(size_t)g[L].second].kind : -1; };
+            if (dir != FFT3D_C2R) {
+                if (kind_at(at) == kBkPlaneR2C) {
+                    want.push_back({kBkPlaneR2C, -1});
+                } else {
+                    want.push_back({kBkRowsR2C, -1});
+                    if (p.n1 > 1) want.push_back({kBkColsFwd, 1});
+                }
+                if (p.n0 > 1) want.push_back({kBkColsFwd, 0});
+                at = want.size();
+            }
+            if (dir != FFT3D_R2C) {
+                if (p.n0 > 1) want.push_back({kBkColsInv, 0});
+                const size_t k = at + (p.n0 > 1 ? 1 : 0);
+                if (kind_at(k) == kBkPlaneC2R) {
+                    want.push_back({kBkPlaneC2R, -1});
+                } else {
+                    if (p.n1 > 1) want.push_back({kBkColsInv, 1});
+                    want.push_back({kBkRowsC2R, -1});
+                }
+            }
+            if (g.size() != want.size()) return fail(who + " has a wrong pass count");
+            const void* cur = (const void*)bb.in.base;
+            for (size_t L = 0; L < g.size(); ++L) {
                 const BatchTask& a = tab.tasks[(size_t)g[L].second];
-                const BatchTask& b = ref.tasks[(size_t)c[L]];
-                if (a.kind != b.kind || a.in != b.in || a.out != b.out || a.ntiles != b.ntiles || a.a0 != b.a0)
-                    return fail("levels: item " + std::to_string(i) + " pass " + std::to_string(L) + " differs");
+                const int axis = (a.kind == kBkColsFwd || a.kind == kBkColsInv) ? (int)(a.s0 - p.d_sched) : -1;
+                if (a.kind != want[L].first || axis != want[L].second)
+                    return fail(who + " pass " + std::to_string(L) + " is not the pass the item runs there");
+                if (a.in != cur) return fail(who + " pass " + std::to_string(L) + " does not read the previous output");
+                cur = a.out;
+                if (dir == FFT3D_ROUNDTRIP && L + 1 == at && cur != (const void*)bb.mid.base)
+                    return fail(who + ": the forward half does not end in mid");
+                if (a.big && (a.kind != kBkPlaneR2C && a.kind != kBkPlaneC2R))
+                    return fail(who + ": a big tile that is not a fused plane");
                 if (L > 0 && g[L].first <= g[L - 1].first)
-                    return fail("levels: item " + std::to_string(i) + " pass " + std::to_string(L) +
-                                " not in a later launch than its predecessor");
+                    return fail(who + " pass " + std::to_string(L) + " not in a later launch than its predecessor");
                 if (L > 0) {
                     const std::vector<int>& d = tab.launches[(size_t)g[L].first].deps;
                     if (std::find(d.begin(), d.end(), g[L - 1].first) == d.end())
                         return fail("levels: a launch does not depend on its tasks' predecessors' launch");
                 }
             }
+            if (cur != (const void*)bb.out.base) return fail(who + ": the last pass does not write the output");
         }
     } else {
         if ((int)tab.task_begin.size() != nq + 1 || tab.task_begin[0] != 0 || tab.task_begin[(size_t)nq] != nt)
@@ -347,7 +375,9 @@ int main(int argc, char** argv)
                 good = good && ok_range(item, lo, len);
                 span(t.out, p0 * rout, np * rout, es, lo, len);
                 good = good && ok_range(item, lo, len);
-                if (np * p.n1 * p.H > (int64_t)kNtSmall * (p.elem == 8 ? 8 : 16)) return fail("plane tile too big");
+                const int64_t ept = t.big ? (p.elem == 8 ? Tier<double>::kEptBig : Tier<float>::kEptBig)
+                                          : (p.elem == 8 ? 8 : 16);
+                if (np * p.n1 * p.H > (int64_t)kNtSmall * ept) return fail("plane tile too big");
                 break;
             }
             case kBkRowsR2C:

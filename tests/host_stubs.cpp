@@ -64,8 +64,8 @@ const void* batch_kernel() { return nullptr; }
 hipError_t batch_occupancy(size_t, int*) { return hipErrorNotSupported; }
 hipError_t launch_batch(unsigned, size_t, const void*, int*, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t init_level() { return hipErrorNotSupported; }
-const void* level_kernel(int, int) { return nullptr; }
-hipError_t launch_level(int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
+const void* level_kernel(int, int, int) { return nullptr; }
+hipError_t launch_level(int, int, int, unsigned, size_t, const BatchTask*, const int*, int, hipStream_t)
 {
     return hipErrorNotSupported;
 }
