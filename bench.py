@@ -633,23 +633,25 @@ def served_samples(F, torch, fields, budget=16 * 10**9):
 # The configurations whose counter bytes profiles/fft3d_pair_traffic.md records.
 TRAFFIC_CONFIGS = (((512, 512, 512), "f32"), ((512, 512, 512), "f64"), ((256, 256, 256), "f64"),
                    ((1024, 1024, 1024), "f32"), ((1024, 1024, 1024), "f64"))
-DEVICE_SOURCES = ("fft3d_kernels.hpp", "fft3d_device.hpp", "fft3d_pruned.hpp", "fft3d_sched.hpp", "fft3d_batch.hpp",
-                  "fft3d_internal.hpp")
+# The sources of the pair's kernels: the two translation units that build
+# them and every header they include.
+DEVICE_SOURCES = ("fft3d_kern_f32.hip", "fft3d_kern_f64.hip", "fft3d_kernels.hpp", "fft3d_device.hpp",
+                  "fft3d_sched.hpp", "fft3d_internal.hpp")
 
 
 def kernel_source_sha256() -> str:
-    """Identity of what the counters measured: the device code (every .hip
-    file and the headers it includes) and the launch shapes of the rule plans
-    of the recorded configurations (their descriptions).  A counter record
-    taken on another identity is stale."""
+    """Identity of what the counters measured: the device code of the pair's
+    kernels (their .hip files and the headers they include) and the launch
+    shapes of the rule plans of the recorded configurations (their
+    descriptions).  A counter record taken on another identity is stale."""
     import hashlib
     from paper_1406_5597_amd import fft3d as F
     d = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith(".hip") or name in DEVICE_SOURCES:
-            h.update(name.encode())
-            h.update(open(os.path.join(d, name), "rb").read())
+    for name in sorted(DEVICE_SOURCES):
+        h.update(name.encode())
+        h.update(open(os.path.join(d, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "fft3d.h"), "rb").read())
     for shape, dt in TRAFFIC_CONFIGS:
         desc = F.Plan(*shape, dtype=dt, host_only=True).describe()
         desc.pop("device", None)
