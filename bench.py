@@ -364,15 +364,10 @@ def run_pruned(F, torch, x64, shape, dtype, steps, warmup, fields, free_ms):
             "GB_s_alg": round(b / (ms * 1e-3) / 1e9, 1), "GB_s_swept": round(bs / (ms * 1e-3) / 1e9, 1)}
 
 
-def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
-    """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
-    32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
-    1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times one
-    persistent launch of the whole batch (graph replay of a batch handle, and
-    the ring-staged fft3d_batch_submit) against the same items launched field
-    by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL), and the launch
-    shape the batch autotuner picks.  Returns (one item per (shape, dtype)
-    with the outputs of the last launch, the record)."""
+def batch_items(F, torch, fields, count=64, seed=4):
+    """The mixed batch's items: `count` fields drawn from fields.batch_mix,
+    uniform[-1,1] values (field i: seed 1000+i), each a ROUNDTRIP item (r2c
+    then c2r with work).  Returns (mix, plans, items, B_alg, real points)."""
     mix = fields.batch_mix(count, seed)
     plans, items = {}, []
     b_alg = 0
@@ -385,6 +380,37 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
         items.append((p, F.FFT3D_ROUNDTRIP, x, F.empty_complex(p), F.empty_real(p), F.empty_complex(p)))
         b_alg += pair_bytes_alg(shape, 4 if dt == "f32" else 8)
         points += shape[0] * shape[1] * shape[2]
+    return mix, plans, items, b_alg, points
+
+
+def batch_traffic_run(F, torch, fields, launches):
+    """For the batch's counter profile (profiles/fft3d_batch_traffic.md): a
+    1 GiB device copy (the counters' calibration), then `launches` launches
+    of the 64-field batch handle; one JSON line."""
+    mix, plans, items, b_alg, points = batch_items(F, torch, fields)
+    handle = F.Batch(items)
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    for _ in range(launches):
+        handle.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    print(json.dumps({"batch_launches": launches, "B_alg": b_alg, "launches": len(handle.describe()["launches"]),
+                      "status": handle.status()}), flush=True)
+    return 0
+
+
+def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
+    """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
+    32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
+    1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times one
+    persistent launch of the whole batch (graph replay of a batch handle, and
+    the ring-staged fft3d_batch_submit) against the same items launched field
+    by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL), and the launch
+    shape the batch autotuner picks.  Returns (one item per (shape, dtype)
+    with the outputs of the last launch, the record)."""
+    mix, plans, items, b_alg, points = batch_items(F, torch, fields, count, seed)
     s = torch.cuda.current_stream()
     handle = F.Batch(items)
 
@@ -709,6 +735,9 @@ def main() -> int:
     ap.add_argument("--no-sizes", action="store_true", help="skip the 256^3 FP64 and 1024^3 lines")
     ap.add_argument("--coop-plane", action="store_true",
                     help="cooperative one-launch plane step for large planes instead of the two kernels")
+    ap.add_argument("--batch-traffic", type=int, default=0, metavar="K",
+                    help="only the batch's counter-profile run: a 1 GiB copy, then K launches of the 64-field "
+                         "batch handle (no metric line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU form (the slab exchange "
@@ -722,6 +751,8 @@ def main() -> int:
     from workloads import fields
 
     F.fft3d_init()  # the device's batch ring
+    if args.batch_traffic > 0:
+        return batch_traffic_run(F, torch, fields, args.batch_traffic)
     n = args.size
     shape = (n, n, n)
     t0 = time.time()
