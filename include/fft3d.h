@@ -335,7 +335,9 @@ int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
  * 0 = clean, bit 1 = a dependency wait hit its spin limit (its tiles
  * skipped), bit 2 = a ticket queue had no workgroup on its XCD (its items
  * did not run), bit 4 = a workgroup's ticket loop ran more iterations than
- * its queue has tickets and was ended. */
+ * its queue has tickets and was ended.  The bits come from the persistent
+ * launch; in level mode (the rule) there are no waits or queues and the
+ * status is always 0. */
 int fft3d_batch_status(fft3d_batch_t b);
 /* JSON: items, tickets, grid, LDS bytes, graph, mode, the level mode's
  * launches as [kind, dtype, tasks, tiles, LDS bytes], and the tasks in ticket
