@@ -665,19 +665,29 @@ DEVICE_SOURCES = ("fft3d_kern_f32.hip", "fft3d_kern_f64.hip", "fft3d_kernels.hpp
                   "fft3d_sched.hpp", "fft3d_internal.hpp")
 
 
+def _code_only(text: str) -> bytes:
+    """Source text without comments and with whitespace collapsed: what the
+    compiler sees (a comment edit leaves the identity unchanged)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split()).encode()
+
+
 def kernel_source_sha256() -> str:
     """Identity of what the counters measured: the device code of the pair's
-    kernels (their .hip files and the headers they include) and the launch
-    shapes of the rule plans of the recorded configurations (their
-    descriptions).  A counter record taken on another identity is stale."""
+    kernels (their .hip files and the headers they include, comments
+    stripped) and the launch shapes of the rule plans of the recorded
+    configurations (their descriptions).  A counter record taken on another
+    identity is stale."""
     import hashlib
     from paper_1406_5597_amd import fft3d as F
     d = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(DEVICE_SOURCES):
         h.update(name.encode())
-        h.update(open(os.path.join(d, name), "rb").read())
-    h.update(open(os.path.join(ROOT, "include", "fft3d.h"), "rb").read())
+        h.update(_code_only(open(os.path.join(d, name)).read()))
+    h.update(_code_only(open(os.path.join(ROOT, "include", "fft3d.h")).read()))
     for shape, dt in TRAFFIC_CONFIGS:
         desc = F.Plan(*shape, dtype=dt, host_only=True).describe()
         desc.pop("device", None)
