@@ -725,7 +725,9 @@ int fft3d_batch_submit_static(const fft3d_batch_item* items, int n, int* status,
                                                    " passes, more than the static scratch holds (" +
                                                    std::to_string(fft3d::kStaticTasks) + ")");
         const size_t img = fft3d::batch_image_bytes(tab);
-        if (img > fft3d::kStaticScratchBytes || !tab.levels)
+        if (!tab.levels)  // the rule; the persistent form would need a counter block
+            return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": runs the level mode only");
+        if (img > fft3d::kStaticScratchBytes)
             return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": task image larger than the static scratch");
         // host staging: this thread's buffer (no device or pinned memory)
         thread_local std::vector<char> host;
