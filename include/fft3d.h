@@ -339,10 +339,11 @@ int fft3d_batch_launch(fft3d_batch_t b, hipStream_t stream);
  * launch; in level mode (the rule) there are no waits or queues and the
  * status is always 0. */
 int fft3d_batch_status(fft3d_batch_t b);
-/* JSON: items, tickets, grid, LDS bytes, graph, mode, the level mode's
- * launches as [kind, dtype, tasks, tiles, LDS bytes], and the tasks in ticket
- * (level mode: launch) order as [kind, dtype, tiles, index of the task
- * waited for, LDS bytes].  Same return convention as fft3d_plan_describe. */
+/* JSON: items, tickets (tiles), grid (the persistent launch's workgroups; 0
+ * in level mode), LDS bytes, graph, mode, the level mode's launches as
+ * [kind, dtype, tasks, tiles, LDS bytes], and the tasks in ticket (level
+ * mode: launch) order as [kind, dtype, tiles, index of the task waited for,
+ * LDS bytes].  Same return convention as fft3d_plan_describe. */
 int fft3d_batch_describe(fft3d_batch_t b, char* buf, size_t len);
 int fft3d_batch_destroy(fft3d_batch_t b);
 

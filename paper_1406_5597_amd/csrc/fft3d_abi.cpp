@@ -809,7 +809,8 @@ int fft3d_batch_create_tuned(const fft3d_batch_item* items, int n, int flags, co
         return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": " + why);
     const int nt = (int)b->tab.tasks.size();
     if (nt > fft3d::kRingTasks) return fail(FFT3D_ERR_UNSUPPORTED, std::string(who) + ": more than 4096 passes");
-    hipError_t e = fft3d::batch_grid(b->tab, b->device, &b->grid);
+    // the persistent launch's workgroups (the level mode launches one per tile)
+    hipError_t e = b->tab.levels ? hipSuccess : fft3d::batch_grid(b->tab, b->device, &b->grid);
     if (e != hipSuccess) return hip_fail(e, who);
     const size_t img = fft3d::batch_image_bytes(b->tab);
     const size_t ctr = (size_t)(fft3d::kBatchCtrHeader + nt) * sizeof(int);
