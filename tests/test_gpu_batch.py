@@ -237,6 +237,9 @@ def test_level_mode_gives_same_bits(F, flags):
     R, C, T = F.FFT3D_R2C, F.FFT3D_C2R, F.FFT3D_ROUNDTRIP
     specs = [(s, d, T, True) for s, d in fields.batch_mix(64, seed=4)]
     specs += [(s, d, T, True) for s, d in BIG_ALONE[:6]]
+    # FP32 lines of radix <= 8 schedules (512 = 8*8*8, 64 = 8*8) run on the
+    # fine column tier alone and on the 512-thread small tier here: same bits
+    specs += [((8, 512, 512), "f32", T, True), ((512, 8, 64), "f32", T, True)]
     specs += [((32, 32, 32), "f64", R, True), ((48, 36, 64), "f32", C, True), ((64, 64, 64), "f64", C, False),
               ((96, 64, 32), "f32", T, False), ((12, 9, 24), "f64", T, True), ((1, 8, 16), "f32", R, True),
               ((8, 1, 8), "f64", C, True), ((1, 1, 2), "f32", T, True)]
