@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <memory>
 #include <mutex>
 
@@ -263,14 +264,12 @@ const char* build_levels(const std::vector<std::vector<BatchTask>>& chains, cons
             pred = &t;
         }
     }
-    // the launch of every pass, for the launches' dependencies
-    std::vector<std::pair<const BatchTask*, int>> where;
+    // the launch of every pass, for the launches' dependencies (std::less:
+    // a total order on pointers into different chains)
+    std::map<const BatchTask*, int, std::less<const BatchTask*>> where;
     for (size_t j = 0; j < g.size(); ++j)
-        for (const BatchTask* t : g[j].tasks) where.push_back({t, (int)j});
-    std::sort(where.begin(), where.end());
-    auto launch_of = [&](const BatchTask* t) {
-        return std::lower_bound(where.begin(), where.end(), std::make_pair(t, -1))->second;
-    };
+        for (const BatchTask* t : g[j].tasks) where[t] = (int)j;
+    auto launch_of = [&](const BatchTask* t) { return where.at(t); };
     for (Group& gr : g) {
         BatchLaunch L;
         for (const BatchTask* pr : gr.preds)
