@@ -404,9 +404,9 @@ def batch_traffic_run(F, torch, fields, launches):
 def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
     """The mixed batch: `count` fields drawn from fields.batch_mix (shapes
     32^3 .. 192x192x96, FP32/FP64), uniform[-1,1] values (field i: seed
-    1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times one
-    persistent launch of the whole batch (graph replay of a batch handle, and
-    the ring-staged fft3d_batch_submit) against the same items launched field
+    1000+i), each a ROUNDTRIP item (r2c then c2r with work).  Times the
+    batched launch of the whole batch (the rule's level mode: graph replay of
+    a batch handle, and the ring-staged fft3d_batch_submit) against the same items launched field
     by field (the items' own kernels, FFT3D_BATCH_SEQUENTIAL), and the launch
     shape the batch autotuner picks.  Returns (one item per (shape, dtype)
     with the outputs of the last launch, the record)."""

@@ -1,4 +1,5 @@
-// fft3d_batch.hip -- one persistent launch for a whole batch of transforms.
+// fft3d_batch.hip -- one persistent launch for a whole batch of transforms
+// (batch modes 1, 2 and 4; the rule is the level mode of fft3d_level.hip).
 //
 // Every item of a batch (forward, inverse or both, any supported shape, FP32
 // or FP64) becomes a chain of tasks, one per pass of the single-item path:

@@ -1,13 +1,13 @@
 // fft3d_level.hip -- the level mode of the batched launch: one launch per
-// pass level, tile kind and dtype.
+// pass level, tile kind, tier and dtype.
 //
 // The host sorts the passes of all items into a sequence of launches such
 // that every pass runs in a later launch than the pass it reads from (stream
 // order is the only synchronisation: no tickets, counters or waits).  A
 // launch runs the tiles of many items' passes of one kind and dtype, one
 // workgroup per tile; its kernel holds that one tile kind only, so it needs
-// the registers of the single-item kernel of that kind, not those of every
-// kind at once (the persistent kernel's 236 VGPRs allow one 512-thread
+// about the registers of the single-item kernel of that kind, not those of
+// every kind at once (the persistent kernel's 223 VGPRs allow one 512-thread
 // workgroup a CU).  The tile functions are those of the single-item kernels:
 // results are bit-identical to the items run alone.
 #include "fft3d_batch.hpp"
