@@ -472,7 +472,7 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
         if (shape, dt) not in seen:
             seen.add((shape, dt))
             samples.append((shape, dt, items[i]))
-    return samples, {
+    rec = {
         "workload": "%d fields (seed %d) of %s, FP32/FP64 mixed (%d FP64), %.1f M real points, ROUNDTRIP "
                     "items" % (count, seed, "/".join("x".join(map(str, sh)) for sh in fields.BATCH_SHAPES),
                                sum(d == "f64" for _, d in mix), points / 1e6),
@@ -485,14 +485,24 @@ def run_batch(F, torch, fields, steps, warmup, count=64, seed=4):
         "GB_s_alg": round(gbs, 1),
         "hbm_frac_alg": round(gbs / HBM_PEAK_GBS, 4),
         "grid": desc["grid"], "tickets": desc["tickets"], "tasks": len(desc["tasks"]), "lds": desc["lds"],
+        "launches": len(desc.get("launches", [])), "mode": desc["mode"],
         "status": status,
         "tuned": {"batch_tuning": bt, "ms_per_launch": round(ms_tuned, 4), "fields_s": round(count * 1e3 / ms_tuned, 1),
                   "GB_s_alg": round(b_alg / (ms_tuned * 1e-3) / 1e9, 1), "speedup_vs_rule": round(ms_graph / ms_tuned, 3),
                   "status": status_tuned, "candidates": len(rep["candidates"])},
         "f32_vs_plain_f64_gpu": fp64_cmp,
     }
-    # (samples: one item per (shape, dtype) with the outputs of the last
-    # launch, for the oracle leg)
+    # counter bytes per launch, from the committed record of the same sources
+    tr = recorded_batch_traffic()
+    if tr and tr.get("B_alg") == b_alg:
+        rec["B_meas_per_launch"] = tr["bytes_per_launch"]
+        rec["meas_over_alg"] = round(tr["bytes_per_launch"] / b_alg, 4)
+        rec["hbm_frac_meas"] = round(tr["bytes_per_launch"] / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    else:
+        rec["B_meas_per_launch"] = None
+    # samples: one item per (shape, dtype) with the outputs of the last
+    # launch, for the oracle leg
+    return samples, rec
 
 
 def served_bytes_alg(shape, dtype, direction, ncomp=3) -> int:
@@ -693,6 +703,40 @@ def kernel_source_sha256() -> str:
         desc.pop("device", None)
         h.update(json.dumps(desc, sort_keys=True).encode())
     return h.hexdigest()
+
+
+# The sources of the level mode's launches and of the batch's tiling: what
+# the batch's counter record (profiles/fft3d_batch_traffic.md) depends on.
+BATCH_SOURCES = ("fft3d_level.hip", "fft3d_batch_tiles.hpp", "fft3d_batch.hpp", "fft3d_kernels.hpp",
+                 "fft3d_device.hpp", "fft3d_sched.hpp", "fft3d_internal.hpp", "fft3d_batch_host.cpp",
+                 "fft3d_batch_host.hpp", "fft3d_plan.cpp")
+
+
+def batch_source_sha256() -> str:
+    """Identity of the batch's counter record: the level mode's device code,
+    the host code that tiles and schedules the batch (comments stripped)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1406_5597_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(BATCH_SOURCES):
+        h.update(name.encode())
+        h.update(_code_only(open(os.path.join(d, name)).read()))
+    h.update(_code_only(open(os.path.join(ROOT, "include", "fft3d.h")).read()))
+    return h.hexdigest()
+
+
+def recorded_batch_traffic():
+    """The batch's HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by
+    the copy calibration) from the committed rocprofv3 summary, if it was
+    taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "fft3d_batch_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+            return rec if rec.get("source_sha256") == batch_source_sha256() else None
+    return None
 
 
 def recorded_traffic():
