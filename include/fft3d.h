@@ -166,6 +166,9 @@ typedef struct {
                             even n2, n2 for odd n2), first stage first, 0-terminated; radices 2, 3,
                             4, 8, 16, 5, 7 with product the axis length; all zero: rule */
     int32_t rows_rpw_inv; /* rows per tile of the inverse rows kernel (split plane step) */
+    int32_t cols_pipe;    /* column passes on the wide tier (tiles of up to 128 KB, one workgroup
+                             per CU): 0 rule, 1 one tile per workgroup, 2 one workgroup per CU that
+                             walks its tiles and loads each one ahead */
 } fft3d_tuning;
 
 enum { FFT3D_TUNE_FUSED = 1, FFT3D_TUNE_SPLIT = 2, FFT3D_TUNE_COOP = 3 };
@@ -183,7 +186,8 @@ int fft3d_plan_tuned(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, c
  * left at the rule are 0).  The search, pass by pass with the plan's own
  * kernels (fft3d_run_pass): rows per tile of each rows kernel; n1 and n0 tile widths and
  * the n0 XCD grouping; the radix schedule of every axis; the plane step
- * (split against cooperative over lags 1..32 and task sizes); the walk
+ * (split against cooperative over lags 1..32 and task sizes); the wide
+ * column passes' persistent loop against one tile per workgroup; the walk
  * order; then whole r2c+c2r pairs of the rule plan against the tuned one (the
  * rule is kept unless the tuned plan is faster).  effort 0: a short search;
  * 1: the full one.  Allocates its own buffers (about 4 x the spectrum's

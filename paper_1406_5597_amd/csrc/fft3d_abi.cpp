@@ -393,6 +393,11 @@ int fft3d_plan_tuned(int64_t n0, int64_t n1, int64_t n2, int dtype, int flags, c
         h->p.d_tw = d;
         h->p.device = dev;
         h->p.has_device = true;
+        e = hipDeviceGetAttribute(&h->p.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) {
+            fft3d_plan_destroy(h);
+            return hip_fail(e, "fft3d_plan: device attributes");
+        }
         const fft3d::AxisSched sched[3] = {p.ax0, p.ax1, p.ax2h};
         e = hipMalloc(&h->p.d_sched, sizeof sched);
         if (e != hipSuccess) {

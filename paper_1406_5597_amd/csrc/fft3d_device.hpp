@@ -284,6 +284,15 @@ __host__ __device__ inline int64_t group_grid(int64_t groups, int64_t g)
     return (int64_t)kXcds * g * ((groups + kXcds - 1) / kXcds);
 }
 
+// Workgroups of a persistent loop over the `virt` indices of such a padded
+// grid: one per CU, a multiple of kXcds (so that indices b and b + k*grid
+// sit on one XCD), at most virt (itself a multiple of kXcds).
+__host__ __device__ inline int64_t pipe_grid(int64_t virt, int cus)
+{
+    int64_t g = cus > kXcds ? cus - cus % kXcds : kXcds;
+    return g < virt ? g : virt;
+}
+
 __device__ __forceinline__ int64_t group_tile(int64_t b, int64_t groups, int64_t g, bool reverse)
 {
     const int64_t x = b % kXcds, k = b / kXcds;
@@ -470,6 +479,8 @@ template <typename T, int LP = LD_PLAIN, int SP = ST_PLAIN> struct ColTileIO {
         const cx<T> v = load_cx<LP, T>(src + p.off);
         return p.ok ? v : mk<T>((T)0, (T)0);
     }
+    // the same load unmasked: a column past `width` reads column width-1
+    __device__ __forceinline__ cx<T> get_unmasked(Pos p) const { return load_cx<LP, T>(src + p.off); }
     __device__ __forceinline__ void put(Pos p, cx<T> v) const
     {
         if (p.ok) store_cx<SP, T>(dst + p.off, v);
@@ -673,6 +684,112 @@ __device__ __forceinline__ void stage(const In& in, const Out& out, const StageA
     if (END) __syncthreads();
 }
 
+// A stage whose input and output cannot alias (no barrier between reads and
+// writes), one butterfly at a time: load, twiddle, butterfly, store.  The
+// same arithmetic as stage(), which first computes all of a thread's
+// butterflies and then stores them; this form holds one butterfly's values
+// in registers instead of EPT, for kernels that keep other values live
+// across the stage (k_cols_pipe).  Plain (unpaired) accesses only.
+template <int R, bool INV, bool LINES_FAST, int NT, int EPT, typename T, class In, class Out>
+__device__ __forceinline__ void stage_direct(const In& in, const Out& out, const StageArg& a,
+                                             const cx<T>* __restrict__ tw)
+{
+    constexpr int KMAX = (EPT + R - 1) / R;
+    const int nb = a.n / R;
+    const int B = nb * a.nlines;
+    const int Ns = a.Ns;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = (int)threadIdx.x + k * NT;
+        if (b < B) {
+            int j, w;
+            butterfly_of<R, LINES_FAST>(b, a, j, w);
+            cx<T> v[R];
+            if constexpr (In::kLinear) {
+                const auto p0 = in.at(w, j);
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = in.get(in.adv(p0, r * nb));
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = in.ld(w, j + r * nb);
+            }
+            const int m = j - fdiv(j, a.mg_ns) * Ns;
+            if (Ns > 1) {
+                const cx<T>* t = tw + m * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[r] = twmul<INV, T>(v[r], t[r - 1]);
+            }
+            dftR<R, INV, T>(v);
+            const int base = (j - m) * R + m;
+            if constexpr (Out::kLinear) {
+                const auto q0 = out.at(w, base);
+#pragma unroll
+                for (int r = 0; r < R; ++r) out.put(out.adv(q0, r * Ns), v[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) out.st(w, base + r * Ns, v[r]);
+            }
+        }
+    }
+}
+
+// A first stage (Ns = 1) in two halves, for column tiles (ColTileIO) whose
+// lines are fast (consecutive threads take consecutive columns; no paired
+// accesses): the loads of a thread's butterflies into registers, then the
+// butterflies and their stores.  stage() does both in one; a persistent loop
+// uses the halves to issue one tile's loads ahead of the previous tile's
+// later stages.  The loads are unmasked and the second half zeroes the
+// columns past the tile's width (what ColTileIO::get does at the load), so
+// that nothing between the two halves waits for the loaded values.
+template <int R, int NT, int EPT> struct FirstStage {
+    static constexpr int K = (EPT + R - 1) / R;
+};
+
+template <int R, int NT, int EPT, typename T, class In>
+__device__ __forceinline__ void first_stage_load(const In& in, const StageArg& a,
+                                                 cx<T> (&v)[FirstStage<R, NT, EPT>::K][R])
+{
+    constexpr int KMAX = FirstStage<R, NT, EPT>::K;
+    const int nb = a.n / R;
+    const int B = nb * a.nlines;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = (int)threadIdx.x + k * NT;
+        if (b < B) {
+            int j, w;
+            butterfly_of<R, true>(b, a, j, w);
+            const auto p0 = in.at(w, j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k][r] = in.get_unmasked(in.adv(p0, r * nb));
+        }
+    }
+}
+
+template <int R, bool INV, int NT, int EPT, typename T, class Out>
+__device__ __forceinline__ void first_stage_finish(const Out& out, const StageArg& a,
+                                                   cx<T> (&v)[FirstStage<R, NT, EPT>::K][R], int width)
+{
+    constexpr int KMAX = FirstStage<R, NT, EPT>::K;
+    const int nb = a.n / R;
+    const int B = nb * a.nlines;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = (int)threadIdx.x + k * NT;
+        if (b < B) {
+            int j, w;
+            butterfly_of<R, true>(b, a, j, w);
+            if (w >= width) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[k][r] = mk<T>((T)0, (T)0);
+            }
+            dftR<R, INV, T>(v[k]);
+            const auto q0 = out.at(w, j * R);
+#pragma unroll
+            for (int r = 0; r < R; ++r) out.put(out.adv(q0, r), v[k][r]);
+        }
+    }
+}
+
 // Largest radix a kernel instantiation carries code for: the fine column
 // tier leaves radix 16 out (the plan gives it radix <= 8 schedules only).
 template <typename T, int NT, int EPT> constexpr int max_radix()
@@ -680,9 +797,11 @@ template <typename T, int NT, int EPT> constexpr int max_radix()
     return (sizeof(T) == 4 && NT == kNtFine && EPT == kEptFine) ? kFineMaxRadix : 16;
 }
 
-template <bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In, class Out>
-__device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
-                                          const In& in, const Out& out, const cx<T>* __restrict__ tw)
+// One stage of any radix the schedule may hold, up to RMAX (code for larger
+// radices is left out).
+template <int RMAX, bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In, class Out>
+__device__ __forceinline__ void stage_upto(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
+                                           const In& in, const Out& out, const cx<T>* __restrict__ tw)
 {
     StageArg a;
     a.n = S.n;
@@ -694,7 +813,7 @@ __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines,
     const cx<T>* t = tw + S.twoff[s];
     switch (S.radix[s]) {
     case 16:
-        if constexpr (max_radix<T, NT, EPT>() >= 16) stage<16, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t);
+        if constexpr (RMAX >= 16) stage<16, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t);
         break;
     case 8: stage<8, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     case 4: stage<4, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
@@ -705,6 +824,41 @@ __device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines,
 #endif
     default: stage<2, INV, LINES_FAST, NT, EPT, MID, END, T>(in, out, a, t); break;
     }
+}
+
+// stage_direct of any radix up to RMAX.
+template <int RMAX, bool INV, bool LINES_FAST, int NT, int EPT, typename T, class In, class Out>
+__device__ __forceinline__ void stage_direct_upto(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
+                                                  const In& in, const Out& out, const cx<T>* __restrict__ tw)
+{
+    StageArg a;
+    a.n = S.n;
+    a.nlines = nlines;
+    a.Ns = S.ns[s];
+    a.mg_lines = mg_lines;
+    a.mg_nb = S.mg_nb[s];
+    a.mg_ns = S.mg_ns[s];
+    const cx<T>* t = tw + S.twoff[s];
+    switch (S.radix[s]) {
+    case 16:
+        if constexpr (RMAX >= 16) stage_direct<16, INV, LINES_FAST, NT, EPT, T>(in, out, a, t);
+        break;
+    case 8: stage_direct<8, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+    case 4: stage_direct<4, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+    case 3: stage_direct<3, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+#if FFT3D_ODD_RADICES
+    case 5: stage_direct<5, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+    case 7: stage_direct<7, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+#endif
+    default: stage_direct<2, INV, LINES_FAST, NT, EPT, T>(in, out, a, t); break;
+    }
+}
+
+template <bool INV, bool LINES_FAST, int NT, int EPT, bool MID, bool END, typename T, class In, class Out>
+__device__ __forceinline__ void stage_any(const AxisSched& S, int s, int nlines, uint32_t mg_lines,
+                                          const In& in, const Out& out, const cx<T>* __restrict__ tw)
+{
+    stage_upto<max_radix<T, NT, EPT>(), INV, LINES_FAST, NT, EPT, MID, END, T>(S, s, nlines, mg_lines, in, out, tw);
 }
 
 // All stages of one axis over `nlines` lines: the first stage reads through

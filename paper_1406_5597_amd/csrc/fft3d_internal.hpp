@@ -48,6 +48,23 @@ template <> struct Tier<double> {
     static constexpr int kRowsWavesFwd = 1;
     static constexpr int kRowsWavesInv = 1;
 };
+// The wide tier's tiles walked by a persistent loop (k_cols_pipe), whose
+// registers hold the next tile's loads beside the current tile's stages.
+// FP32: the wide tier's 1024 threads of 16 elements (128 VGPRs; a few spill).
+// FP64: 512 threads of 16 elements (two waves per SIMD, 256 VGPRs, no
+// spills; on 1024 threads the FP64 kernel spilled some 100 registers and
+// ran 40% slower than the one-tile kernel).  Measured at 1024^3 with 512
+// threads for both, FP32 pairs were 12.6 ms against 12.0 ms on 1024.
+template <typename T> struct PipeTier;
+template <> struct PipeTier<float> {
+    static constexpr int kNt = kNtWide;
+    static constexpr int kEpt = Tier<float>::kEptSmall;
+};
+template <> struct PipeTier<double> {
+    static constexpr int kNt = kNtWide / 2;
+    static constexpr int kEpt = 2 * Tier<double>::kEptSmall;
+};
+
 // Waves-per-SIMD bound of a rows kernel: the small tier's, none for the big.
 template <typename T, int EPT, bool INV> constexpr int rows_waves()
 {
@@ -73,6 +90,7 @@ struct ColPass {
     bool big = false;     // kernel tier: big, or
     bool wide = false;    // ... wide (column kernels only), else small
     bool fine = false;    // small tile on the fine tier (FP32, radix <= 8)
+    bool pipe = false;    // wide tiles walked by a persistent loop (k_cols_pipe)
     size_t lds = 0;       // dynamic LDS bytes
 };
 
@@ -138,6 +156,7 @@ struct Plan {
     // device state
     bool has_device = false;
     int device = -1;
+    int cus = 0;               // compute units of the device
     void* d_tw = nullptr;
 
     std::string describe() const;

@@ -237,6 +237,125 @@ __global__ __launch_bounds__(NT, (cols_waves<T, NT, EPT>())) void k_cols(const c
     col_tile<T, NT, EPT, INV>(in + b * bstride + c0, out + b * bstride + c0, S, width, W, mg_w, *axp, tw, buf);
 }
 
+// Twiddles of the stages after the first of an axis schedule (the first has
+// none): complex values from the start of the axis's table.
+__host__ __device__ inline int later_twiddles(const AxisSched& ax)
+{
+    return ax.nst > 1 ? ax.twoff[ax.nst - 1] + ax.ns[ax.nst - 1] * (ax.radix[ax.nst - 1] - 1) : 0;
+}
+
+// The wide column tiles (128 KB, one workgroup per CU, so no second
+// workgroup overlaps one's loads with another's arithmetic) as a persistent
+// loop: each workgroup walks the tiles k_cols's grid would hand to workgroups
+// blockIdx.x, blockIdx.x + gridDim.x, ... (gridDim.x a multiple of the XCD
+// count, so every tile stays on the XCD it had), and loads the next tile's
+// first-stage inputs into registers while the current tile runs its LDS
+// stages and stores.  R0: the first stage's radix; needs two stages or more,
+// the later ones of radix <= kPipeMaxRadix (the registers of the loads in
+// flight leave no room for radix-16 code).  Same tiles, same arithmetic and
+// results as k_cols.
+//
+// The wait for a load also waits for every memory access issued before it,
+// so nothing between issuing the next tile's loads and using them may wait
+// on memory: the later stages load nothing from global memory (their
+// twiddles sit in LDS after the tile, copied once), the loads are unmasked
+// until they are used (first_stage_load), and spill reloads stay out of the
+// stages (the FP32 kernel spills a few registers, reloaded where the tile
+// index is computed).  Dynamic LDS: the tile, then later_twiddles(ax)
+// complex values.
+template <typename T, int NT, int EPT, bool INV, int R0>
+__global__ __launch_bounds__(NT, 1) void k_cols_pipe(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
+                                                     const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
+                                                     int64_t bstride, int W, uint32_t mg_w, int64_t tiles_per_batch,
+                                                     int64_t ntiles, int64_t ngroups, int gsize, int reverse,
+                                                     int64_t nvirt)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    LdsIO<T> l;
+    l.buf = buf;
+    l.L.nlines = W;
+    l.L.lpp = W;
+    l.L.sp = 0;
+    l.L.sw = 1;
+    l.L.si = W;
+    l.L.mg_lines = mg_w;
+    l.L.mg_lpp = mg_w;
+    cx<T>* twl = buf + (int64_t)axp->n * W;
+    {
+        const int ntw = later_twiddles(*axp);
+        for (int i = (int)threadIdx.x; i < ntw; i += NT) twl[i] = tw[i];
+        // (the first barrier of the loop orders these writes before any read)
+    }
+    auto first_arg = [&](const AxisSched& ax) {
+        StageArg a;
+        a.n = ax.n;
+        a.nlines = W;
+        a.Ns = 1;
+        a.mg_lines = mg_w;
+        a.mg_nb = ax.mg_nb[0];
+        a.mg_ns = ax.mg_ns[0];
+        return a;
+    };
+    // the next real tile at or after virtual workgroup index vb (padding
+    // indices map past the tile count); nvirt when none is left
+    auto next_tile = [&](int64_t vb, int64_t& t) {
+        for (; vb < nvirt; vb += gridDim.x) {
+            t = group_tile(vb, ngroups, gsize, reverse);
+            if (t < ntiles) break;
+        }
+        return vb;
+    };
+    auto tile_io = [&](int64_t t) {
+        const int64_t b = t / tiles_per_batch;
+        const int64_t c0 = (t - b * tiles_per_batch) * W;
+        const int64_t rem = ncols - c0;
+        ColTileIO<T> g;
+        g.src = in + b * bstride + c0;
+        g.dst = out + b * bstride + c0;
+        g.S = S;
+        g.width = rem < (int64_t)W ? (int)rem : W;
+        return g;
+    };
+    int64_t t = 0;
+    int64_t vb = next_tile(blockIdx.x, t);
+    if (vb >= nvirt) return;
+    ColTileIO<T> g = tile_io(t);
+    cx<T> v[FirstStage<R0, NT, EPT>::K][R0];
+    first_stage_load<R0, NT, EPT, T>(g, first_arg(*axp), v);
+    for (;;) {
+        // What the stages derive from the schedule, the twiddles and the
+        // thread index is the same for every tile; the compiler would hoist
+        // all of it out of the loop and hold it in registers across tiles
+        // (spilling).  An offset of zero that it cannot see through, added
+        // to both pointers once per tile, keeps that work inside the loop.
+        int zero = 0;
+        asm volatile("" : "+s"(zero));
+        const AxisSched& ax = axp[zero];
+        const cx<T>* twq = twl + zero;
+        const StageArg a0 = first_arg(ax);
+        // the next tile's index first: the loads in flight complete before
+        // anything here that waits on memory (a spill reload) holds them up
+        int64_t tn = 0;
+        const int64_t vn = next_tile(vb + gridDim.x, tn);
+        first_stage_finish<R0, INV, NT, EPT, T>(l, a0, v, g.width);
+        __syncthreads();
+        ColTileIO<T> gn = g;
+        if (vn < nvirt) {
+            gn = tile_io(tn);
+            first_stage_load<R0, NT, EPT, T>(gn, a0, v);  // in flight during the stages below
+        }
+        const int nst = ax.nst;
+        for (int s = 1; s < nst - 1; ++s)
+            stage_upto<kPipeMaxRadix, INV, true, NT, EPT, true, true, T>(ax, s, W, mg_w, l, l, twq);
+        stage_direct_upto<kPipeMaxRadix, INV, true, NT, EPT, T>(ax, nst - 1, W, mg_w, l, g, twq);
+        if (vn >= nvirt) break;
+        __syncthreads();  // the last stage's LDS reads before the next tile's writes
+        vb = vn;
+        g = gn;
+    }
+}
+
 // Split-plane forward: rpw real rows of length n2 -> rpw rows of H bins.
 template <typename T, int NT, int EPT>
 __global__ __launch_bounds__(NT, (rows_waves<T, EPT, false>())) void k_rows_r2c(const T* x, cx<T>* X, const AxisSched* __restrict__ axp,
@@ -800,6 +919,10 @@ template <typename T> hipError_t init_plain()
     FFT3D_ALLOW((k_cols<T, kNtBig, EB, true>));
     FFT3D_ALLOW((k_cols<T, kNtWide, ES, false>));
     FFT3D_ALLOW((k_cols<T, kNtWide, ES, true>));
+    FFT3D_ALLOW((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, false, 16>));
+    FFT3D_ALLOW((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, true, 16>));
+    FFT3D_ALLOW((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, false, 8>));
+    FFT3D_ALLOW((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, true, 8>));
     if constexpr (sizeof(T) == 4) {
         FFT3D_ALLOW((k_cols<T, kNtFine, kEptFine, false>));
         FFT3D_ALLOW((k_cols<T, kNtFine, kEptFine, true>));
@@ -949,7 +1072,24 @@ hipError_t cols_t(const Plan& p, const ColPass& cp, int axis, int64_t tw_off, co
         hipLaunchKernelGGL((k_cols<T, kNtBig, EB, INV>), dim3(grid), dim3(kNtBig), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);
-    else if (cp.wide)
+    else if (cp.wide && cp.pipe) {
+        // persistent: one workgroup per CU, at most one per tile group slot
+        const int64_t pgrid = pipe_grid(grid, p.cus);
+        const AxisSched& hax = axis == 0 ? p.ax0 : p.ax1;
+        const int r0 = hax.radix[0];
+        const size_t lds = cp.lds + (size_t)later_twiddles(hax) * sizeof(cx<T>);
+        if (lds > (size_t)kLdsMax) return hipErrorInvalidConfiguration;
+        if (r0 == 16)
+            hipLaunchKernelGGL((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, INV, 16>), dim3(pgrid), dim3(PipeTier<T>::kNt), lds, st, ci, co,
+                               ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W, div_magic((uint32_t)cp.W),
+                               cp.tiles_per_batch, ntiles, ngroups, gsize, rev, (int64_t)grid);
+        else if (r0 == 8)
+            hipLaunchKernelGGL((k_cols_pipe<T, PipeTier<T>::kNt, PipeTier<T>::kEpt, INV, 8>), dim3(pgrid), dim3(PipeTier<T>::kNt), lds, st, ci, co,
+                               ax, table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W, div_magic((uint32_t)cp.W),
+                               cp.tiles_per_batch, ntiles, ngroups, gsize, rev, (int64_t)grid);
+        else
+            return hipErrorInvalidConfiguration;  // the plan marks first stages of radix 16 or 8 only
+    } else if (cp.wide)
         hipLaunchKernelGGL((k_cols<T, kNtWide, ES, INV>), dim3(grid), dim3(kNtWide), cp.lds, st, ci, co, ax,
                            table<T>(p, tw_off), cp.S, cp.ncols, cp.bstride, cp.W,
                            div_magic((uint32_t)cp.W), cp.tiles_per_batch, ntiles, ngroups, gsize, rev);

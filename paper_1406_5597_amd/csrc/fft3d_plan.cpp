@@ -258,6 +258,16 @@ static void mark_fine(ColPass& cp, const AxisSched& ax)
     cp.fine = ok;
 }
 
+// A wide tile of a schedule whose first stage has radix 16 or 8, with more
+// stages after it of radix <= kPipeMaxRadix, runs as the persistent loop of
+// k_cols_pipe.
+static void mark_pipe(ColPass& cp, const AxisSched& ax, bool on)
+{
+    bool ok = on && cp.wide && ax.nst >= 2 && (ax.radix[0] == 16 || ax.radix[0] == 8);
+    for (int i = 1; i < ax.nst; ++i) ok = ok && ax.radix[i] <= kPipeMaxRadix;
+    cp.pipe = ok;
+}
+
 bool small_colpass(const Plan& p, int axis, ColPass& cp)
 {
     const int cxs = 2 * p.elem;
@@ -559,6 +569,14 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         mark_fine(p.pass0t, p.ax0);
         if (!p.fused_plane) mark_fine(p.pass1, p.ax1);
     }
+    if (tu.cols_pipe < 0 || tu.cols_pipe > 2) {
+        why = "tuning: cols_pipe must be 0, 1 or 2";
+        return FFT3D_ERR_INVALID_ARG;
+    }
+    const bool pipe = tu.cols_pipe != 1;
+    mark_pipe(p.pass0, p.ax0, pipe);
+    mark_pipe(p.pass0t, p.ax0, pipe);
+    if (!p.fused_plane) mark_pipe(p.pass1, p.ax1, pipe);
     return FFT3D_OK;
 }
 
@@ -573,13 +591,13 @@ static std::string sched_json(const AxisSched& s)
 
 static std::string pass_json(const ColPass& c)
 {
-    char b[320];
+    char b[384];
     snprintf(b, sizeof b,
              "{\"row_stride\": %lld, \"ncols\": %lld, \"nbatch\": %lld, \"batch_stride\": %lld, "
-             "\"W\": %d, \"tier\": \"%s\", \"grid\": %lld, \"lds\": %zu}",
+             "\"W\": %d, \"tier\": \"%s\", \"grid\": %lld, \"lds\": %zu, \"pipe\": %s}",
              (long long)c.S, (long long)c.ncols, (long long)c.nbatch, (long long)c.bstride, c.W,
              c.big ? "big" : (c.wide ? "wide" : (c.fine ? "fine" : "small")), (long long)(c.nbatch * c.tiles_per_batch),
-             c.lds);
+             c.lds, c.pipe ? "true" : "false");
     return b;
 }
 
@@ -630,12 +648,13 @@ std::string Plan::describe() const
     r += "\"r2c_passes\": " + f + "], \"c2r_passes\": " + i + "5], ";
     // the tuning the plan was built with (fft3d_plan_tuned), or null
     if (tuned) {
-        char t[256];
+        char t[384];
         snprintf(t, sizeof t,
                  "\"tuning\": {\"plane\": %d, \"rows_rpw\": %d, \"rows_rpw_inv\": %d, \"n1_w\": %d, \"n0_w\": %d, "
-                 "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
+                 "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, "
+                 "\"cols_pipe\": %d, \"radix\": [",
                  tuning.plane, tuning.rows_rpw, tuning.rows_rpw_inv, tuning.n1_w, tuning.n0_w, tuning.n0_group,
-                 tuning.walk, tuning.coop_lag, tuning.coop_rpw, tuning.coop_w);
+                 tuning.walk, tuning.coop_lag, tuning.coop_rpw, tuning.coop_w, tuning.cols_pipe);
         r += t;
         for (int a = 0; a < 3; ++a) {
             r += a ? ", [" : "[";

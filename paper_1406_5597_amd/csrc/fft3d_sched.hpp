@@ -15,6 +15,9 @@ constexpr int kMaxStages = 12;
 constexpr int kNtFine = 1024;
 constexpr int kEptFine = 8;
 constexpr int kFineMaxRadix = 8;
+// Largest radix after the first stage of a pipelined wide column pass
+// (k_cols_pipe).
+constexpr int kPipeMaxRadix = 8;
 
 // Division by an invariant d in [1, 2^16) of an index n with n*d < 2^32:
 // n / d = mulhi32(n, magic(d)) with magic(d) = floor(2^32/d) + 1, and

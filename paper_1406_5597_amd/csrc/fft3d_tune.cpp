@@ -85,12 +85,13 @@ bool device_arch(std::string& arch)
 
 void put_tuning(std::string& o, const fft3d_tuning& t)
 {
-    char b[256];
+    char b[384];
     snprintf(b, sizeof b,
              "{\"plane\": %d, \"rows_rpw\": %d, \"rows_rpw_inv\": %d, \"n1_w\": %d, \"n0_w\": %d, "
-             "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, \"radix\": [",
+             "\"n0_group\": %d, \"walk\": %d, \"coop_lag\": %d, \"coop_rpw\": %d, \"coop_w\": %d, "
+             "\"cols_pipe\": %d, \"radix\": [",
              t.plane, t.rows_rpw, t.rows_rpw_inv, t.n1_w, t.n0_w, t.n0_group, t.walk, t.coop_lag, t.coop_rpw,
-             t.coop_w);
+             t.coop_w, t.cols_pipe);
     o += b;
     for (int a = 0; a < 3; ++a) {
         o += a ? ", [" : "[";
@@ -268,7 +269,7 @@ bool read_tuning(const JVal& o, fft3d_tuning& t)
         !int_field(o, "rows_rpw_inv", t.rows_rpw_inv) || !int_field(o, "n1_w", t.n1_w) ||
         !int_field(o, "n0_w", t.n0_w) || !int_field(o, "n0_group", t.n0_group) || !int_field(o, "walk", t.walk) ||
         !int_field(o, "coop_lag", t.coop_lag) || !int_field(o, "coop_rpw", t.coop_rpw) ||
-        !int_field(o, "coop_w", t.coop_w))
+        !int_field(o, "coop_w", t.coop_w) || !int_field(o, "cols_pipe", t.cols_pipe))
         return false;
     if (const JVal* r = o.get("radix")) {
         if (r->k != JVal::Arr || r->arr.size() != 3) return false;
@@ -762,8 +763,25 @@ int fft3d_autotune(int64_t n0, int64_t n1, int64_t n2, int dtype, int effort, ff
         const double ms = S.eval(t, split_ps, "plane", "{\"plane\": \"split\"}");
         if (better(ms, inc)) cur = t;
     }
-    // 6. walk order, on whole pairs
+    // 6. wide column passes: the persistent loop that loads a tile ahead
+    //    against one tile per workgroup, on whole pairs
     const std::vector<int> pair = {-1};
+    {
+        bool pipe = false;
+        fft3d_plan_t h = nullptr;
+        if (fft3d_plan_tuned(n0, n1, n2, dtype, FFT3D_PLAN_HOST_ONLY, &cur, &h) == FFT3D_OK) {
+            pipe = h->p.pass0.pipe || (!h->p.fused_plane && h->p.pass1.pipe);
+            (void)fft3d_plan_destroy(h);
+        }
+        if (pipe) {
+            const double inc = S.eval(cur, pair, "cols_pipe", "{\"cols_pipe\": \"rule\"}");
+            fft3d_tuning t = cur;
+            t.cols_pipe = 1;
+            const double ms = S.eval(t, pair, "cols_pipe", "{\"cols_pipe\": 1}");
+            if (better(ms, inc)) cur = t;
+        }
+    }
+    // 7. walk order, on whole pairs
     {
         double inc = S.eval(cur, pair, "walk", "{\"walk\": \"rule\"}");
         int pick = 0;
@@ -782,7 +800,7 @@ int fft3d_autotune(int64_t n0, int64_t n1, int64_t n2, int dtype, int effort, ff
         }
         cur.walk = pick;
     }
-    // 7. the rule plan against the tuned one, whole pairs
+    // 8. the rule plan against the tuned one, whole pairs
     const fft3d_tuning zero{};
     const double ms_rule = S.eval(zero, pair, "final", "{\"plan\": \"rule\"}");
     std::string tj;

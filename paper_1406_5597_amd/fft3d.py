@@ -78,7 +78,7 @@ class BatchItem(ctypes.Structure):
 # the scalar fields of fft3d_tuning; the struct holds radix[3][8] between
 # coop_w and rows_rpw_inv
 TUNING_FIELDS = ("plane", "rows_rpw", "n1_w", "n0_w", "n0_group", "walk", "coop_lag", "coop_rpw", "coop_w",
-                 "rows_rpw_inv")
+                 "rows_rpw_inv", "cols_pipe")
 
 
 class Tuning(ctypes.Structure):

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from workloads import fields
-from tests.gpu_util import TOL, dev_cplx, dev_real, host, rel_l2, rounded, say
+from tests.gpu_util import TOL, dev_cplx, dev_real, host, oracle_threads, rel_l2, rounded, say
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,35 @@ def test_tile_tunings_bit_identical_to_rule(F, oracle, shape, dtype):
         X, y = pair(F, p, x, S)
         assert same_bits(X, X0), t
         assert same_bits(y, y0), t
+
+
+# Wide column tiles (1024-long columns) walked by the persistent loop that
+# loads a tile ahead (the rule) against one tile per workgroup: more tiles
+# than workgroups (each workgroup walks several), a ragged last tile, n0
+# passes over one block and n1 passes over several planes.
+PIPE_SHAPES = [(1024, 98, 84), (10, 1024, 1024), (1024, 3, 18)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", PIPE_SHAPES)
+def test_pipelined_wide_columns(F, oracle, shape, dtype):
+    say("pipelined wide columns %s %s" % (shape, dtype))
+    x64 = rounded(fields.uniform(shape, seed=83), dtype)
+    rule = F.Plan(*shape, dtype=dtype)
+    plain = F.Plan(*shape, dtype=dtype, tuning=dict(cols_pipe=1))
+    d, dp = rule.describe(), plain.describe()
+    for desc, pipe in ((d, True), (dp, False)):
+        passes = [desc["n0_pass"]] + ([desc["plane"]["n1_pass"]] if "n1_pass" in desc["plane"] else [])
+        wide = [c for c in passes if c["tier"] == "wide"]
+        assert wide and all(c["pipe"] == pipe for c in wide)
+    x = dev_real(x64, dtype)
+    Xo = oracle.r2c(x64, threads=oracle_threads())
+    S = dev_cplx(rounded(Xo, dtype), dtype)
+    X0, y0 = pair(F, rule, x, S)
+    X1, y1 = pair(F, plain, x, S)
+    assert same_bits(X0, X1) and same_bits(y0, y1)
+    assert rel_l2(host(X0), Xo) <= TOL[dtype]
+    assert rel_l2(host(y0), oracle.c2r(rounded(Xo, dtype), shape[2], threads=oracle_threads())) <= TOL[dtype]
 
 
 RADIX_TUNINGS = [

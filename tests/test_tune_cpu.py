@@ -70,6 +70,24 @@ def test_fine_column_tier(F):
     assert desc(F, (1024, 64, 64), n0_w=16)["n0_pass"]["tier"] == "wide"
 
 
+def test_pipelined_wide_column_passes(F):
+    # wide tiles of schedules with a radix-16/8 first stage and radix <= 8
+    # after it walk their tiles in a persistent loop by rule; cols_pipe=1
+    # gives one tile per workgroup
+    for dt in ("f32", "f64"):
+        d = F.Plan(1024, 1024, 1024, dtype=dt, host_only=True).describe()
+        assert d["schedules"]["n0"]["radices"] == [16, 8, 8]
+        for c in (d["n0_pass"], d["plane"]["n1_pass"]):
+            assert c["tier"] == "wide" and c["pipe"] is True
+        d = desc(F, (1024, 1024, 1024), dtype=dt, cols_pipe=1)
+        assert not d["n0_pass"]["pipe"] and not d["plane"]["n1_pass"]["pipe"] and d["tuning"]["cols_pipe"] == 1
+    # a later radix-16 stage, or a tier other than wide, keeps one tile per workgroup
+    assert not desc(F, (1024, 64, 64), radix=[[8, 8, 16], [], []])["n0_pass"]["pipe"]
+    assert not F.Plan(768, 4, 4, dtype="f32", host_only=True).describe()["n0_pass"]["pipe"]
+    d = F.Plan(512, 512, 512, dtype="f32", host_only=True).describe()
+    assert not d["n0_pass"]["pipe"] and not d["plane"]["n1_pass"]["pipe"]
+
+
 def test_plane_kinds(F):
     assert desc(F, (512, 512, 512), plane=F.FFT3D_TUNE_COOP, coop_lag=16, coop_rpw=10, coop_w=8)["plane"]["coop"] == {
         "row_tasks": 52, "col_tasks": 33, "rows_per_task": 10, "cols_per_task": 8, "lag": 16, "grid": 0,
@@ -99,6 +117,7 @@ def test_radix_schedules(F):
     (dict(coop_lag=4), "coop_"), (dict(plane=3, coop_lag=300), "coop_lag"), (dict(plane=3, coop_rpw=21), "coop_rpw"),
     (dict(plane=3, coop_w=3), "coop_w"), (dict(radix=[[16, 16, 4], [], []]), "radix[0]"),
     (dict(radix=[[], [6, 64, 1], []]), "radix[1]"), (dict(radix=[[], [], [32, 8]]), "radix[2]"),
+    (dict(cols_pipe=3), "cols_pipe"), (dict(cols_pipe=-1), "cols_pipe"),
 ])
 def test_tunings_refused(F, tuning, needle):
     with pytest.raises(F.Fft3dError) as e:
