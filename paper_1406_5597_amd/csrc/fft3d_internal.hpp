@@ -50,11 +50,11 @@ template <> struct Tier<double> {
 };
 // The wide tier's tiles walked by a persistent loop (k_cols_pipe), whose
 // registers hold the next tile's loads beside the current tile's stages.
-// FP32: the wide tier's 1024 threads of 16 elements (128 VGPRs; a few spill).
-// FP64: 512 threads of 16 elements (two waves per SIMD, 256 VGPRs, no
-// spills; on 1024 threads the FP64 kernel spilled some 100 registers and
-// ran 40% slower than the one-tile kernel).  Measured at 1024^3 with 512
-// threads for both, FP32 pairs were 12.6 ms against 12.0 ms on 1024.
+// FP32: the wide tier's 1024 threads of 16 elements (at most 128 VGPRs).
+// FP64: 512 threads of 16 elements (two waves per SIMD, at most 256 VGPRs;
+// on 1024 threads the FP64 kernel spilled some 100 registers and ran 40%
+// slower than the one-tile kernel).  Measured at 1024^3 with 512 threads
+// for both, FP32 pairs were 12.6 ms against 12.0 ms on 1024.
 template <typename T> struct PipeTier;
 template <> struct PipeTier<float> {
     static constexpr int kNt = kNtWide;

@@ -259,10 +259,9 @@ __host__ __device__ inline int later_twiddles(const AxisSched& ax)
 // so nothing between issuing the next tile's loads and using them may wait
 // on memory: the later stages load nothing from global memory (their
 // twiddles sit in LDS after the tile, copied once), the loads are unmasked
-// until they are used (first_stage_load), and spill reloads stay out of the
-// stages (the FP32 kernel spills a few registers, reloaded where the tile
-// index is computed).  Dynamic LDS: the tile, then later_twiddles(ax)
-// complex values.
+// until they are used (first_stage_load), and the kernel must not spill (a
+// spill reload is such a wait).  Dynamic LDS: the tile, then
+// later_twiddles(ax) complex values.
 template <typename T, int NT, int EPT, bool INV, int R0>
 __global__ __launch_bounds__(NT, 1) void k_cols_pipe(const cx<T>* in, cx<T>* out, const AxisSched* __restrict__ axp,
                                                      const cx<T>* __restrict__ tw, int64_t S, int64_t ncols,
@@ -272,83 +271,106 @@ __global__ __launch_bounds__(NT, 1) void k_cols_pipe(const cx<T>* in, cx<T>* out
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    LdsIO<T> l;
-    l.buf = buf;
-    l.L.nlines = W;
-    l.L.lpp = W;
-    l.L.sp = 0;
-    l.L.sw = 1;
-    l.L.si = W;
-    l.L.mg_lines = mg_w;
-    l.L.mg_lpp = mg_w;
     cx<T>* twl = buf + (int64_t)axp->n * W;
     {
         const int ntw = later_twiddles(*axp);
         for (int i = (int)threadIdx.x; i < ntw; i += NT) twl[i] = tw[i];
         // (the first barrier of the loop orders these writes before any read)
     }
-    auto first_arg = [&](const AxisSched& ax) {
+    // What the stages derive from the schedule, the tile width, the
+    // twiddles and the thread index is the same for every tile; the compiler
+    // would hoist all of it out of the loop and hold it in registers across
+    // tiles (spilling).  Every such input is taken once per tile through an
+    // offset of zero that the compiler cannot see through (Loop), which keeps
+    // that work inside the loop.
+    struct Loop {
+        const AxisSched* ax;
+        const cx<T>* tw;
+        int W, gsize;
+        uint32_t mg_w;
+        int64_t tpb;
+    };
+    auto loop_inputs = [&]() {
+        int zero = 0;
+        asm volatile("" : "+s"(zero));
+        Loop q;
+        q.ax = axp + zero;
+        q.tw = twl + zero;
+        q.W = W + zero;
+        q.gsize = gsize + zero;
+        q.mg_w = mg_w + (uint32_t)zero;
+        q.tpb = tiles_per_batch + zero;
+        return q;
+    };
+    auto lds_io = [&](const Loop& q) {
+        LdsIO<T> l;
+        l.buf = buf;
+        l.L.nlines = q.W;
+        l.L.lpp = q.W;
+        l.L.sp = 0;
+        l.L.sw = 1;
+        l.L.si = q.W;
+        l.L.mg_lines = q.mg_w;
+        l.L.mg_lpp = q.mg_w;
+        return l;
+    };
+    auto first_arg = [&](const Loop& q) {
         StageArg a;
-        a.n = ax.n;
-        a.nlines = W;
+        a.n = q.ax->n;
+        a.nlines = q.W;
         a.Ns = 1;
-        a.mg_lines = mg_w;
-        a.mg_nb = ax.mg_nb[0];
-        a.mg_ns = ax.mg_ns[0];
+        a.mg_lines = q.mg_w;
+        a.mg_nb = q.ax->mg_nb[0];
+        a.mg_ns = q.ax->mg_ns[0];
         return a;
     };
     // the next real tile at or after virtual workgroup index vb (padding
     // indices map past the tile count); nvirt when none is left
-    auto next_tile = [&](int64_t vb, int64_t& t) {
+    auto next_tile = [&](const Loop& q, int64_t vb, int64_t& t) {
         for (; vb < nvirt; vb += gridDim.x) {
-            t = group_tile(vb, ngroups, gsize, reverse);
+            t = group_tile(vb, ngroups, q.gsize, reverse);
             if (t < ntiles) break;
         }
         return vb;
     };
-    auto tile_io = [&](int64_t t) {
-        const int64_t b = t / tiles_per_batch;
-        const int64_t c0 = (t - b * tiles_per_batch) * W;
+    auto tile_io = [&](const Loop& q, int64_t t) {
+        const int64_t b = t / q.tpb;
+        const int64_t c0 = (t - b * q.tpb) * q.W;
         const int64_t rem = ncols - c0;
         ColTileIO<T> g;
         g.src = in + b * bstride + c0;
         g.dst = out + b * bstride + c0;
         g.S = S;
-        g.width = rem < (int64_t)W ? (int)rem : W;
+        g.width = rem < (int64_t)q.W ? (int)rem : q.W;
         return g;
     };
     int64_t t = 0;
-    int64_t vb = next_tile(blockIdx.x, t);
+    Loop q = loop_inputs();
+    int64_t vb = next_tile(q, blockIdx.x, t);
     if (vb >= nvirt) return;
-    ColTileIO<T> g = tile_io(t);
+    ColTileIO<T> g = tile_io(q, t);
     cx<T> v[FirstStage<R0, NT, EPT>::K][R0];
-    first_stage_load<R0, NT, EPT, T>(g, first_arg(*axp), v);
+    first_stage_load<R0, NT, EPT, T>(g, first_arg(q), v);
     for (;;) {
-        // What the stages derive from the schedule, the twiddles and the
-        // thread index is the same for every tile; the compiler would hoist
-        // all of it out of the loop and hold it in registers across tiles
-        // (spilling).  An offset of zero that it cannot see through, added
-        // to both pointers once per tile, keeps that work inside the loop.
-        int zero = 0;
-        asm volatile("" : "+s"(zero));
-        const AxisSched& ax = axp[zero];
-        const cx<T>* twq = twl + zero;
-        const StageArg a0 = first_arg(ax);
+        q = loop_inputs();
+        const AxisSched& ax = *q.ax;
+        const LdsIO<T> l = lds_io(q);
+        const StageArg a0 = first_arg(q);
         // the next tile's index first: the loads in flight complete before
         // anything here that waits on memory (a spill reload) holds them up
         int64_t tn = 0;
-        const int64_t vn = next_tile(vb + gridDim.x, tn);
+        const int64_t vn = next_tile(q, vb + gridDim.x, tn);
         first_stage_finish<R0, INV, NT, EPT, T>(l, a0, v, g.width);
         __syncthreads();
         ColTileIO<T> gn = g;
         if (vn < nvirt) {
-            gn = tile_io(tn);
+            gn = tile_io(q, tn);
             first_stage_load<R0, NT, EPT, T>(gn, a0, v);  // in flight during the stages below
         }
         const int nst = ax.nst;
         for (int s = 1; s < nst - 1; ++s)
-            stage_upto<kPipeMaxRadix, INV, true, NT, EPT, true, true, T>(ax, s, W, mg_w, l, l, twq);
-        stage_direct_upto<kPipeMaxRadix, INV, true, NT, EPT, T>(ax, nst - 1, W, mg_w, l, g, twq);
+            stage_upto<kPipeMaxRadix, INV, true, NT, EPT, true, true, T>(ax, s, q.W, q.mg_w, l, l, q.tw);
+        stage_direct_upto<kPipeMaxRadix, INV, true, NT, EPT, T>(ax, nst - 1, q.W, q.mg_w, l, g, q.tw);
         if (vn >= nvirt) break;
         __syncthreads();  // the last stage's LDS reads before the next tile's writes
         vb = vn;

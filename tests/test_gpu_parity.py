@@ -219,7 +219,7 @@ def test_batch_submit_matches_alone(F):
 
 
 TRANSPOSED_SHAPES = [(2, 3, 4), (1, 8, 16), (8, 1, 8), (12, 9, 24), (32, 32, 32), (48, 36, 64), (96, 64, 32),
-                     (24, 256, 256), (128, 128, 128), (3, 1024, 1024)]
+                     (24, 256, 256), (128, 128, 128), (3, 1024, 1024), (1024, 4, 36)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
