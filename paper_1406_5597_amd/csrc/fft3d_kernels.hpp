@@ -237,13 +237,6 @@ __global__ __launch_bounds__(NT, (cols_waves<T, NT, EPT>())) void k_cols(const c
     col_tile<T, NT, EPT, INV>(in + b * bstride + c0, out + b * bstride + c0, S, width, W, mg_w, *axp, tw, buf);
 }
 
-// Twiddles of the stages after the first of an axis schedule (the first has
-// none): complex values from the start of the axis's table.
-__host__ __device__ inline int later_twiddles(const AxisSched& ax)
-{
-    return ax.nst > 1 ? ax.twoff[ax.nst - 1] + ax.ns[ax.nst - 1] * (ax.radix[ax.nst - 1] - 1) : 0;
-}
-
 // The wide column tiles (128 KB, one workgroup per CU, so no second
 // workgroup overlaps one's loads with another's arithmetic) as a persistent
 // loop: each workgroup walks the tiles k_cols's grid would hand to workgroups

@@ -260,10 +260,11 @@ static void mark_fine(ColPass& cp, const AxisSched& ax)
 
 // A wide tile of a schedule whose first stage has radix 16 or 8, with more
 // stages after it of radix <= kPipeMaxRadix, runs as the persistent loop of
-// k_cols_pipe.
-static void mark_pipe(ColPass& cp, const AxisSched& ax, bool on)
+// k_cols_pipe when the tile and the later stages' twiddles fit LDS together.
+static void mark_pipe(ColPass& cp, const AxisSched& ax, bool on, int cxs)
 {
-    bool ok = on && cp.wide && ax.nst >= 2 && (ax.radix[0] == 16 || ax.radix[0] == 8);
+    bool ok = on && cp.wide && ax.nst >= 2 && (ax.radix[0] == 16 || ax.radix[0] == 8) &&
+              cp.lds + (size_t)later_twiddles(ax) * (size_t)cxs <= (size_t)kLdsMax;
     for (int i = 1; i < ax.nst; ++i) ok = ok && ax.radix[i] <= kPipeMaxRadix;
     cp.pipe = ok;
 }
@@ -574,9 +575,9 @@ int plan_build_host(Plan& p, int64_t n0, int64_t n1, int64_t n2, int dtype, int 
         return FFT3D_ERR_INVALID_ARG;
     }
     const bool pipe = tu.cols_pipe != 1;
-    mark_pipe(p.pass0, p.ax0, pipe);
-    mark_pipe(p.pass0t, p.ax0, pipe);
-    if (!p.fused_plane) mark_pipe(p.pass1, p.ax1, pipe);
+    mark_pipe(p.pass0, p.ax0, pipe, cxs);
+    mark_pipe(p.pass0t, p.ax0, pipe, cxs);
+    if (!p.fused_plane) mark_pipe(p.pass1, p.ax1, pipe, cxs);
     return FFT3D_OK;
 }
 

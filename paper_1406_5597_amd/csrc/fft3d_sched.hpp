@@ -44,6 +44,13 @@ struct AxisSched {
 // different LDS banks.
 inline constexpr int pad16_host(int i) { return i + (i >> 4); }
 
+// Twiddles of the stages after the first of an axis schedule (the first has
+// none): complex values from the start of the axis's table.
+inline constexpr int later_twiddles(const AxisSched& ax)
+{
+    return ax.nst > 1 ? ax.twoff[ax.nst - 1] + ax.ns[ax.nst - 1] * (ax.radix[ax.nst - 1] - 1) : 0;
+}
+
 // Lines in LDS: element i of line w lives at
 //   (w / lpp) * sp + (w % lpp) * sw + i * si.
 // LINES_FAST: consecutive threads take consecutive lines (use when sw == 1),

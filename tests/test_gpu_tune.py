@@ -97,6 +97,25 @@ def test_pipelined_wide_columns(F, oracle, shape, dtype):
     assert rel_l2(host(y0), oracle.c2r(rounded(Xo, dtype), shape[2], threads=oracle_threads())) <= TOL[dtype]
 
 
+def test_pipelined_wide_columns_four_stages(F, oracle):
+    # 2048-long columns on the wide tier (8 columns a tile, ragged last tile)
+    # with a four-stage schedule: twiddles of three later stages in LDS
+    shape, t = (2048, 6, 10), dict(n0_w=8, radix=[[8, 8, 8, 4], [], []])
+    say("pipelined wide columns %s %s" % (shape, t))
+    x64 = rounded(fields.uniform(shape, seed=85), "f32")
+    a = F.Plan(*shape, dtype="f32", tuning=t)
+    b = F.Plan(*shape, dtype="f32", tuning=dict(t, cols_pipe=1))
+    assert a.describe()["n0_pass"]["pipe"] and not b.describe()["n0_pass"]["pipe"]
+    x = dev_real(x64, "f32")
+    Xo = oracle.r2c(x64)
+    S = dev_cplx(rounded(Xo, "f32"), "f32")
+    X0, y0 = pair(F, a, x, S)
+    X1, y1 = pair(F, b, x, S)
+    assert same_bits(X0, X1) and same_bits(y0, y1)
+    assert rel_l2(host(X0), Xo) <= TOL["f32"]
+    assert rel_l2(host(y0), oracle.c2r(rounded(Xo, "f32"), shape[2])) <= TOL["f32"]
+
+
 RADIX_TUNINGS = [
     ((512, 64, 256), dict(radix=[[16, 16, 2], [], []])),
     ((512, 64, 256), dict(radix=[[2, 16, 16], [4, 16], [8, 16]])),

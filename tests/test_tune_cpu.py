@@ -86,6 +86,12 @@ def test_pipelined_wide_column_passes(F):
     assert not F.Plan(768, 4, 4, dtype="f32", host_only=True).describe()["n0_pass"]["pipe"]
     d = F.Plan(512, 512, 512, dtype="f32", host_only=True).describe()
     assert not d["n0_pass"]["pipe"] and not d["plane"]["n1_pass"]["pipe"]
+    # the tile and the later stages' twiddles must fit LDS together: 128 KB +
+    # 2040 FP32 twiddles (16 KB) do, 128 KB + 4088 FP64 twiddles (64 KB) do not
+    d = desc(F, (2048, 4, 4), n0_w=8, radix=[[8, 8, 8, 4], [], []])
+    assert d["n0_pass"]["tier"] == "wide" and d["n0_pass"]["pipe"]
+    d = desc(F, (4096, 4, 4), dtype="f64", n0_w=2, radix=[[8, 8, 8, 8], [], []])
+    assert d["n0_pass"]["tier"] == "wide" and not d["n0_pass"]["pipe"]
 
 
 def test_plane_kinds(F):
