@@ -172,6 +172,30 @@ def test_autotune_table_and_tuned_plan(F, oracle, tmp_path, shape, dtype):
     assert rel_l2(host(y), oracle.c2r(rounded(Xo, dtype), shape[2])) <= TOL[dtype]
 
 
+def test_autotune_times_the_persistent_column_loop(F, oracle):
+    # a shape with wide column passes: the search times the loop against one
+    # tile per workgroup, and whichever it keeps matches the oracle
+    shape = (1024, 16, 18)
+    say("autotune with wide column passes %s" % (shape,))
+    best, report = F.autotune(shape, "f32", effort=0)
+    stages = [c for c in report["candidates"] if c["stage"] == "cols_pipe"]
+    # the stage runs when the tiling chosen before it has a persistent pass
+    # (the earlier stages may have moved the n0 pass off the wide tier)
+    d = F.Plan(*shape, dtype="f32", host_only=True, tuning=dict(best, cols_pipe=0)).describe()
+    say("tuned %s, persistent n0 pass before the stage: %s" % (best, d["n0_pass"]["pipe"]))
+    if d["n0_pass"]["pipe"]:
+        assert len(stages) == 2 and all(c["ms"] and c["ms"] > 0 for c in stages)
+    else:
+        assert not stages and best["cols_pipe"] == 0
+    assert best["cols_pipe"] in (0, 1)
+    p = F.Plan(*shape, dtype="f32", tuning=best)
+    x64 = rounded(fields.uniform(shape, seed=87), "f32")
+    Xo = oracle.r2c(x64)
+    X, y = pair(F, p, dev_real(x64, "f32"), dev_cplx(rounded(Xo, "f32"), "f32"))
+    assert rel_l2(host(X), Xo) <= TOL["f32"]
+    assert rel_l2(host(y), oracle.c2r(rounded(Xo, "f32"), shape[2])) <= TOL["f32"]
+
+
 def test_batch_autotune_gives_same_bits(F):
     import torch
     mix = fields.batch_mix(8, seed=79)
