@@ -248,9 +248,10 @@ __global__ __launch_bounds__(NT, (cols_waves<T, NT, EPT>())) void k_cols(const c
 // flight leave no room for radix-16 code).  Same tiles, same arithmetic and
 // results as k_cols.
 //
-// The wait for a load also waits for every memory access issued before it,
-// so nothing between issuing the next tile's loads and using them may wait
-// on memory: the later stages load nothing from global memory (their
+// Vector memory accesses complete on one in-order counter (vmcnt): waiting
+// for one load waits for every global or scratch access issued before it.
+// So nothing between issuing the next tile's loads and using them may wait
+// on such an access: the later stages load nothing from global memory (their
 // twiddles sit in LDS after the tile, copied once), the loads are unmasked
 // until they are used (first_stage_load), and the kernel must not spill (a
 // spill reload is such a wait).  Dynamic LDS: the tile, then
